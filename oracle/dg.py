@@ -1,0 +1,196 @@
+"""The upwind-DG convection operator, its SSP-RK3 substeps and helpers, written out plainly.
+
+Test infrastructure (see ``oracle/__init__``).
+
+State layout: coefficients c[T, i, m] (element T, velocity component i, basis function m of the
+orthonormal Dubiner basis pulled back through the element map), FP64.
+
+Operator (Sec. 2.3, upwind trilinear form; Sec. 2.4, discrete operator C^V; Sec. 3.2,
+propagation problem):
+
+    C_h(u; w, z) = sum_T [ - int_T (w (x) u) : grad z dx + int_{dT} (u.n) w^ z ds ]
+    r = -(M^V)^-1 C^V(u) w          (the time derivative in  ds w + (M^V)^-1 C^V w = 0)
+
+with w^ the upwind value (the trace of w taken from the side the flow comes from) and M^V the
+DG mass matrix, diagonal for an L2-orthogonal basis (Sec. 2.3).
+
+Readings where the paper leaves the hot path open (each also listed in the design doc):
+  * The paper's convecting velocity is H(div)-conforming, so u.n is single-valued.  For a
+    discontinuous convecting field we use the facet-averaged normal velocity
+    beta = 1/2 (u^- + u^+) . n^-, and w^ = w^- if beta > 0 else w^+ (at beta = 0 the flux is 0
+    for either choice).
+  * "Self" mode u := w gives the nonlinear div(w (x) w); a caller-given u gives the linear
+    operator C^V(u) of the propagation problem with frozen convection.
+  * The upwind value is taken pointwise at the facet quadrature points, so the facet rule
+    (refelem.facet_rule, canonical orientation from mesh.Mesh) is part of the definition.
+  * Time integrator: three-stage SSP-RK3 (Shu-Osher form); the paper leaves the explicit
+    integrator of the propagation problem generic.
+"""
+import numpy as np
+
+from . import refelem as R
+
+
+class Space:
+    """Vector DG space V_h = prod_T [P^k(T)]^d on a mesh, with the oracle's quadrature."""
+
+    def __init__(self, mesh, k, chunk=8192):
+        self.mesh = mesh
+        self.k = k
+        self.dim = d = mesh.dim
+        self.np = R.n_basis(d, k)
+        self.vq, self.vw = R.collapsed_rule(d, R.volume_points_for_oracle(k))
+        self.phi_v = R.eval_basis(d, k, self.vq)  # [Q, Np]
+        self.dphi_v = R.eval_grad(d, k, self.vq)  # [Q, Np, d]
+        self.fq, self.fw = R.facet_rule(d, R.facet_points(k))  # [Qf, d-1], weights sum to 1
+        self.chunk = chunk
+        # the diagonal of M^V: int_T phi_m phi_m dx, by quadrature on every element
+        self.mass = mesh.absdetJ[:, None] * np.einsum("q,qm,qm->m", self.vw, self.phi_v,
+                                                      self.phi_v)[None, :]
+        self._cache = {}
+        self._cached_bytes = 0
+
+    @property
+    def shape(self):
+        return (self.mesh.E, self.dim, self.np)
+
+    # ---- facet points ------------------------------------------------------------------
+    def facet_points_phys(self, T, f):
+        """Physical facet quadrature points of local facet f of elements T (own frame)."""
+        V = self.mesh.canon[T, f]  # [n, d, d], canonical vertex order
+        x = V[:, None, 0, :] + np.einsum("qc,ncj->nqj", self.fq, V[:, 1:, :] - V[:, None, 0, :])
+        return x  # [n, Qf, d]
+
+    def _ref_coords(self, T, x):
+        """Reference coordinates of physical points x [n, Q, d] in elements T."""
+        m = self.mesh
+        return np.einsum("nij,nqj->nqi", m.Jinv[T], x - m.X[T, None, 0, :])
+
+    def facet_basis(self, T):
+        """phi_m at the facet points, own side and neighbour side: two [n, d+1, Qf, Np]."""
+        key = (T[0], T[-1], len(T))
+        if key in self._cache:
+            return self._cache[key]
+        m, d = self.mesh, self.dim
+        own, nbr = [], []
+        for f in range(d + 1):
+            x = self.facet_points_phys(T, f)
+            N = m.nbr[T, f]
+            xn = x - m.shift[T, f][:, None, :]
+            own.append(R.eval_basis(d, self.k, self._ref_coords(T, x)))
+            nbr.append(R.eval_basis(d, self.k, self._ref_coords(N, xn)))
+        out = (np.stack(own, axis=1), np.stack(nbr, axis=1))
+        nbytes = len(T) * (d + 1) * len(self.fw) * self.np * 16
+        if nbytes < 1e9 and self._cached_bytes + nbytes < 4e9:
+            self._cache[key] = out
+            self._cached_bytes += nbytes
+        return out
+
+    # ---- the operator ------------------------------------------------------------------
+    def form(self, w, u=None, elems=None):
+        """C_h(u; w, phi_{T,i,m}) for the test functions of elements `elems` -> [n, d, Np]."""
+        m, d = self.mesh, self.dim
+        uu = w if u is None else u
+        elems = np.arange(m.E) if elems is None else np.asarray(elems)
+        out = np.empty((len(elems), d, self.np))
+        for s in range(0, len(elems), self.chunk):
+            T = elems[s:s + self.chunk]
+            # volume term: - int_T w_i u_j d_j phi_m dx
+            wq = np.einsum("qm,tim->tqi", self.phi_v, w[T])
+            uq = np.einsum("qm,tim->tqi", self.phi_v, uu[T])
+            grad = np.einsum("tkj,qmk->tqmj", m.Jinv[T], self.dphi_v)  # physical gradients
+            conv = np.einsum("tqj,tqmj->tqm", uq, grad)  # u . grad phi_m
+            vol = -np.einsum("t,q,tqi,tqm->tim", m.absdetJ[T], self.vw, wq, conv)
+            # facet term: int_dT (u.n) w^ phi_m ds with the pointwise upwind value
+            pown, pnbr = self.facet_basis(T)
+            fac = np.zeros_like(vol)
+            for f in range(d + 1):
+                N = m.nbr[T, f]
+                wm = np.einsum("tqm,tim->tqi", pown[:, f], w[T])
+                wp = np.einsum("tqm,tim->tqi", pnbr[:, f], w[N])
+                um = np.einsum("tqm,tim->tqi", pown[:, f], uu[T])
+                up = np.einsum("tqm,tim->tqi", pnbr[:, f], uu[N])
+                beta = 0.5 * np.einsum("tqj,tj->tq", um + up, m.normal[T, f])
+                what = np.where(beta[..., None] > 0.0, wm, wp)
+                fac += np.einsum("t,q,tq,tqi,tqm->tim", m.area[T, f], self.fw, beta, what,
+                                 pown[:, f])
+            out[s:s + self.chunk] = vol + fac
+        return out
+
+    def apply(self, w, u=None, elems=None):
+        """r = -(M^V)^-1 C^V(u) w on elements `elems` (all by default); u=None means u := w."""
+        elems = np.arange(self.mesh.E) if elems is None else np.asarray(elems)
+        return -self.form(w, u, elems) / self.mass[elems][:, None, :]
+
+    def ssprk3(self, w, dt, n, u=None):
+        """n substeps of three-stage SSP-RK3 for ds w = apply(w) (Shu-Osher form)."""
+        w = np.array(w, dtype=np.float64, copy=True)
+        for _ in range(n):
+            w1 = w + dt * self.apply(w, u)
+            w2 = 0.75 * w + 0.25 * (w1 + dt * self.apply(w1, u))
+            w = w / 3.0 + 2.0 / 3.0 * (w2 + dt * self.apply(w2, u))
+        return w
+
+    # ---- projection and functionals ----------------------------------------------------
+    def quad_points(self, n):
+        """Physical points of a collapsed rule with n points per direction: [E, Q, d]."""
+        p, _ = R.collapsed_rule(self.dim, n)
+        return self.mesh.X[:, None, 0, :] + np.einsum("tij,qj->tqi", self.mesh.J, p)
+
+    def project(self, vals, n):
+        """L2 projection onto V_h of a field given at quad_points(n): vals [E, Q, d]."""
+        p, wq = R.collapsed_rule(self.dim, n)
+        phi = R.eval_basis(self.dim, self.k, p)
+        rhs = np.einsum("t,q,tqi,qm->tim", self.mesh.absdetJ, wq, vals, phi)
+        return rhs / self.mass[:, None, :]
+
+    def evaluate(self, w, pts_ref):
+        """w at reference points [Q, d] of every element -> [E, Q, d]."""
+        phi = R.eval_basis(self.dim, self.k, pts_ref)
+        return np.einsum("qm,tim->tqi", phi, w)
+
+    def energy(self, w):
+        """1/2 int |w|^2 dx by quadrature."""
+        wq = np.einsum("qm,tim->tqi", self.phi_v, w)
+        return 0.5 * np.einsum("t,q,tqi,tqi->", self.mesh.absdetJ, self.vw, wq, wq)
+
+    def momentum(self, w):
+        """int w dx (vector) by quadrature."""
+        wq = np.einsum("qm,tim->tqi", self.phi_v, w)
+        return np.einsum("t,q,tqi->i", self.mesh.absdetJ, self.vw, wq)
+
+    def l2_norm(self, w):
+        return np.sqrt(2.0 * self.energy(w))
+
+    def rel_l2(self, a, b):
+        """||a - b||_L2 / ||b||_L2."""
+        return self.l2_norm(a - b) / self.l2_norm(b)
+
+    def max_speed(self, w, n=None):
+        """max over the points of a volume rule of the Euclidean norm of w."""
+        n = R.volume_points_for_oracle(self.k) if n is None else n
+        p, _ = R.collapsed_rule(self.dim, n)
+        return float(np.max(np.linalg.norm(self.evaluate(w, p), axis=-1)))
+
+    def dissipation(self, w, u):
+        """1/2 sum_F int_F |beta| |w^- - w^+|^2 ds (each facet once), the upwind dissipation."""
+        m, d = self.mesh, self.dim
+        T = np.arange(m.E)
+        pown, pnbr = self.facet_basis(T)
+        tot = 0.0
+        for f in range(d + 1):
+            N = m.nbr[T, f]
+            wm = np.einsum("tqm,tim->tqi", pown[:, f], w[T])
+            wp = np.einsum("tqm,tim->tqi", pnbr[:, f], w[N])
+            um = np.einsum("tqm,tim->tqi", pown[:, f], u[T])
+            up = np.einsum("tqm,tim->tqi", pnbr[:, f], u[N])
+            beta = 0.5 * np.einsum("tqj,tj->tq", um + up, m.normal[T, f])
+            jump2 = np.sum((wm - wp) ** 2, axis=-1)
+            # every facet is visited from both sides: weight 1/2 each
+            tot += 0.5 * np.einsum("t,q,tq,tq->", m.area[T, f], self.fw, np.abs(beta), jump2)
+        return 0.5 * tot
+
+
+def cfl_dt(h, k, umax, c=0.1):
+    """dt = c h / (k^2 max|u|), the substep size of the benchmark configurations."""
+    return c * h / (max(k, 1) ** 2 * umax)
