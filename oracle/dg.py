@@ -61,24 +61,27 @@ class Space:
         x = V[:, None, 0, :] + np.einsum("qc,ncj->nqj", self.fq, V[:, 1:, :] - V[:, None, 0, :])
         return x  # [n, Qf, d]
 
-    def _ref_coords(self, T, x):
-        """Reference coordinates of physical points x [n, Q, d] in elements T."""
-        m = self.mesh
-        return np.einsum("nij,nqj->nqi", m.Jinv[T], x - m.X[T, None, 0, :])
+    def facet_ref_points(self, T, f):
+        """The facet quadrature points of local facet f of elements T in their reference
+        coordinates: the affine map sends reference vertices to element vertices, so the
+        point A + s(B-A) [+ t(C-A)] of the canonically ordered facet vertices is the same
+        combination of the corresponding reference vertices (no rounding from J^-1)."""
+        vref = R.ref_vertices(self.dim)
+        ci = self.mesh.canon_idx[T, f]  # [n, d] local ids in canonical order
+        A = vref[ci[:, 0]]
+        return A[:, None, :] + np.einsum("qc,ncj->nqj", self.fq, vref[ci[:, 1:]] - A[:, None, :])
 
     def facet_basis(self, T):
         """phi_m at the facet points, own side and neighbour side: two [n, d+1, Qf, Np]."""
-        key = (T[0], T[-1], len(T))
+        key = hash(np.ascontiguousarray(T).tobytes())
         if key in self._cache:
             return self._cache[key]
         m, d = self.mesh, self.dim
         own, nbr = [], []
         for f in range(d + 1):
-            x = self.facet_points_phys(T, f)
             N = m.nbr[T, f]
-            xn = x - m.shift[T, f][:, None, :]
-            own.append(R.eval_basis(d, self.k, self._ref_coords(T, x)))
-            nbr.append(R.eval_basis(d, self.k, self._ref_coords(N, xn)))
+            own.append(R.eval_basis(d, self.k, self.facet_ref_points(T, f)))
+            nbr.append(R.eval_basis(d, self.k, self.facet_ref_points(N, m.nbr_facet[T, f])))
         out = (np.stack(own, axis=1), np.stack(nbr, axis=1))
         nbytes = len(T) * (d + 1) * len(self.fw) * self.np * 16
         if nbytes < 1e9 and self._cached_bytes + nbytes < 4e9:

@@ -52,6 +52,7 @@ class Mesh:
         normal = np.zeros((E, nf, d))
         area = np.zeros((E, nf))
         canon = np.zeros((E, nf, d, d))  # canonical vertex coordinates (unwrapped, own frame)
+        canon_idx = np.zeros((E, nf, d), dtype=np.int64)  # their local vertex ids
         for f in range(nf):
             V = self.X[:, self.facet_vertices(f), :]  # [E, d, d]
             cen[:, f] = V.mean(axis=1)
@@ -68,11 +69,13 @@ class Mesh:
             sgn = np.sign(np.einsum("ej,ej->e", nvec, opp))
             normal[:, f] = -sgn[:, None] * nvec
             area[:, f] = meas
-            canon[:, f] = _lex_sort_vertices(V)
+            canon[:, f], order = _lex_sort_vertices(V)
+            canon_idx[:, f] = np.array(self.facet_vertices(f))[order]
         self.centroid = cen
         self.normal = normal
         self.area = area
         self.canon = canon
+        self.canon_idx = canon_idx
         # match facets by centroid modulo the period
         flat = cen.reshape(-1, d) % self.period
         flat = np.where(np.abs(flat - self.period) < 1e-12 * self.period, 0.0, flat)
@@ -94,11 +97,15 @@ class Mesh:
 
 
 def _lex_sort_vertices(V, rtol=1e-10):
-    """Sort the d vertices of each facet lexicographically by coordinate. V: [E, d, d]."""
+    """Sort the d vertices of each facet lexicographically by coordinate. V: [E, d, d].
+
+    Returns the sorted coordinates and, per facet, the positions (0..d-1) of the sorted
+    vertices in the input order."""
     E, nvert, d = V.shape
     scale = np.max(np.abs(V[:, 1:] - V[:, :1])) + 1e-300
     tol = rtol * scale
     out = V.copy()
+    order = np.tile(np.arange(nvert), (E, 1))
     # simple insertion sort over the (at most 3) vertices, vectorised over facets
     for i in range(1, nvert):
         for j in range(i, 0, -1):
@@ -113,7 +120,10 @@ def _lex_sort_vertices(V, rtol=1e-10):
                 decided |= gt | lt
             out[swap, j - 1] = b[swap]
             out[swap, j] = a[swap]
-    return out
+            oa = order[:, j - 1].copy()
+            order[swap, j - 1] = order[swap, j]
+            order[swap, j] = oa[swap]
+    return out, order
 
 
 def box_mesh(dim, N, jitter=0.0, seed=0):

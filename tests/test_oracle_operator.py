@@ -49,6 +49,11 @@ def test_facet_points_coincide_from_both_sides(dim, N, jit):
         x = sp.facet_points_phys(T, f)
         xn = sp.facet_points_phys(m.nbr[T, f], m.nbr_facet[T, f])
         assert np.abs(x - (xn + m.shift[T, f][:, None, :])).max() < 1e-14
+        # the reference-frame points used by the operator map onto the same physical points
+        for TT, ff, sh in ((T, f, 0.0), (m.nbr[T, f], m.nbr_facet[T, f], m.shift[T, f])):
+            xi = sp.facet_ref_points(TT, ff)
+            xp = m.X[TT, None, 0, :] + np.einsum("nij,nqj->nqi", m.J[TT], xi)
+            assert np.abs(xp + (sh[:, None, :] if np.ndim(sh) else 0.0) - x).max() < 1e-14
 
 
 # ---------------------------------------------------------------- invariants
