@@ -1,0 +1,192 @@
+"""Benchmark: SSP-RK3 substeps of the upwind-DG convection operator on one MI355X.
+
+Workload (default): 2D periodic unit square, 256x256 squares x 2 triangles (131072 affine
+triangles), vector P4 DG (15 basis functions per component), FP64, self-convection
+div(w (x) w); initial field = L2 projection of the Taylor-Green field plus seeded N(0, 1e-3)
+coefficient noise; dt = 0.1 h / (k^2 max|u|).  One step = one SSP-RK3 substep (three fused
+operator-plus-stage launches).  Inputs are resident in device memory when timing starts.
+
+Prints one JSON line.  `--gpus N` with N > 1 is not supported (this benchmark runs on one GPU).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64 = 78.6e12  # MI355X FP64 vector (= FP64 matrix) peak, flop/s
+PEAK_FP32 = 157.3e12
+PEAK_HBM = 8.0e12
+
+CONFIGS = {
+    "c1": dict(dim=2, n=16, k=2, field="tg"),
+    "c2": dict(dim=2, n=256, k=4, field="tg"),
+    "c3": dict(dim=3, n=32, k=3, field="tg"),
+    "c4": dict(dim=3, n=64, k=2, field="fourier"),
+    "c5": dict(dim=2, n=128, k=3, field="fourier"),
+}
+
+
+def shape_counts(dim, k):
+    np_ = (k + 1) * (k + 2) // 2 if dim == 2 else (k + 1) * (k + 2) * (k + 3) // 6
+    nv = max(1, (3 * k + 1) // 2)
+    nf = max(1, (3 * k + 2) // 2)
+    nq = nv ** dim
+    nfq = nf ** (dim - 1)
+    return np_, nq, nfq
+
+
+def alg_flops_per_elem(dim, k):
+    """Algorithmic flops of one fused operator+stage application per element (dense
+    per-element contractions, minimal exact volume rule, each facet trace once per side)."""
+    NP, NQ, NFQ = shape_counts(dim, k)
+    NF = dim + 1
+    interp = 2 * dim * NP * NQ
+    uhat = 2 * dim * dim * NQ
+    test = 4 * dim * NP * NQ          # P_m = uh . Dv_m, then R_im += w_i P_m
+    trace = 2 * dim * NP * NFQ * NF   # own-side traces
+    lift = 2 * dim * NP * NFQ * NF
+    flux = (8 * dim + 3) * NFQ * NF
+    rk = 4 * dim * NP
+    return interp + uhat + test + trace + lift + flux + rk
+
+
+def alg_bytes_per_elem(dim, k, stage_reads_w0=True, esz=8):
+    """Algorithmic HBM bytes of one fused application per element: read x (neighbours
+    counted once), read w0 (stages 2, 3), write out, geometry (J^-1, neighbour ids, list)."""
+    NP, _, _ = shape_counts(dim, k)
+    state = dim * NP * esz
+    geo = dim * dim * esz + 4 * (dim + 1) + 4
+    return state * (3 if stage_reads_w0 else 2) + geo
+
+
+def make_state(dg, cfg, seed=0):
+    from paper_1508_04245_amd import synth
+    m = dg.Mesh.box(cfg["dim"], cfg["n"], cfg["k"])
+    n = cfg["k"] + 3
+    x = m.project_points(n)
+    if cfg["field"] == "tg":
+        f = synth.taylor_green_2d(x) if cfg["dim"] == 2 else synth.taylor_green_3d(x)
+    else:
+        f = synth.FourierField(cfg["dim"], seed=seed)(x)
+    w = m.project(f, n) + synth.noise(m.shape, seed=seed)
+    return m, w
+
+
+def cpu_baseline(cfg, budget_s=30.0):
+    """The FP64 oracle, as it stands, on the same mesh: one untimed warm application, then
+    timed applications of the full operator until the budget is used; DOF-updates/s with one
+    SSP-RK3 substep = 3 applications."""
+    from oracle.dg import Space
+    from oracle.mesh import box_mesh
+    from paper_1508_04245_amd import synth
+    sp = Space(box_mesh(cfg["dim"], cfg["n"]), cfg["k"])
+    w = synth.noise(sp.shape, seed=0, sd=1.0)
+    sp.apply(w)
+    t0, c0 = time.perf_counter(), time.process_time()
+    n = 0
+    while True:
+        sp.apply(w)
+        n += 1
+        if time.perf_counter() - t0 > budget_s / 2:
+            break
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    ndof = int(np.prod(sp.shape))
+    return {"value": ndof * n / 3.0 / wall, "unit": "DOF-updates/s",
+            "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
+            "sample": "%d full operator application(s) of the FP64 NumPy oracle on the same "
+                      "mesh after one warm call (%.1f s), scaled to SSP-RK3 substeps "
+                      "(3 applications each); %d logical CPUs visible"
+                      % (n, wall, len(os.sched_getaffinity(0)))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=30.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (the multi-GPU sharding is a design in DESIGN.md,"
+              " not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1508_04245_amd as dg
+    dg.lib()
+    cfg = CONFIGS[args.config]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    m, w_host = make_state(dg, cfg)
+    ty = torch.float64 if args.precision == "fp64" else torch.float32
+    w = torch.tensor(w_host, dtype=ty, device=dev)
+    w64 = torch.tensor(w_host, dtype=torch.float64, device=dev)
+    umax = float(m.reduce("maxvel", w64)[0].item())
+    h = 1.0 / cfg["n"]
+    dt = 0.1 * h / (max(cfg["k"], 1) ** 2 * umax)
+    stream = torch.cuda.current_stream()
+    work = torch.empty((2,) + tuple(w.shape), dtype=ty, device=dev)
+    m.rk_substeps(w, dt, args.warmup, work=work)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    m.rk_substeps(w, dt, args.steps, work=work)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    ndof = m.info["n_dof"]
+    value = ndof * args.steps / gpu_s
+    launches = 3 * args.steps
+    per_launch = gpu_s / max(1, launches)
+    E = m.info["n_elem"]
+    flops = alg_flops_per_elem(cfg["dim"], cfg["k"]) * E
+    byts = alg_bytes_per_elem(cfg["dim"], cfg["k"], esz=8 if ty == torch.float64 else 4) * E
+    peak = PEAK_FP64 if ty == torch.float64 else PEAK_FP32
+    finite = torch.isfinite(w).all().item()
+    out = {
+        "metric": "DG convection DOF-updates/s (SSP-RK3 substeps), FP64",
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": gpu_s * 1e3 / max(1, args.steps),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if ty == torch.float64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D periodic unit square %dx%d x2 triangles (%d), vector P%d DG "
+                               "(%d dofs/component), self-convection, SSP-RK3 dt=%.4g"
+                               % (cfg["n"], cfg["n"], E, cfg["k"], m.np, dt)
+                   if cfg["dim"] == 2 else
+                   "3D periodic unit cube %d^3 x6 tets (%d), vector P%d DG, SSP-RK3 dt=%.4g"
+                   % (cfg["n"], E, cfg["k"], dt),
+                   "config": args.config, "n_dof": ndof, "precision": args.precision},
+        "roofline": {"bound": "alu", "achieved": flops / per_launch / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": flops / per_launch / peak, "traffic": None,
+                     "kernel": "conv_kernel<%d,%d,%s,self>" % (cfg["dim"], cfg["k"], args.precision),
+                     "launch_us": per_launch * 1e6,
+                     "hbm_equiv_GBps": byts / per_launch / 1e9},
+        "wall_s": wall,
+        "final_state_finite": bool(finite),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

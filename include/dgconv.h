@@ -1,0 +1,145 @@
+/* dgconv.h - C ABI of the MI355X upwind-DG convection library (libdgconv.so).
+ *
+ * The library computes the explicit upwind discontinuous-Galerkin convection operator and
+ * its explicit Runge-Kutta substeps on affine simplicial meshes (triangles, tetrahedra):
+ *
+ *   C_h(u; w, z) = sum_T [ -int_T (w (x) u) : grad z dx + int_dT (u.n) w^ z ds ]   (Sec. 2.3)
+ *   r            = -(M^V)^-1 C^V(u) w                                              (Sec. 2.4)
+ *   ds w + (M^V)^-1 C^V(u) w = 0   integrated by SSP-RK3 substeps        (Sec. 3.2, propagation)
+ *
+ * w^ is the upwind value (pointwise, at the facet quadrature points), M^V the DG mass matrix,
+ * diagonal for the orthonormal element basis (Sec. 2.3).  Where the paper's convecting
+ * velocity is H(div)-conforming, a discontinuous convecting field here enters the facet term
+ * through its averaged normal component beta = 1/2 (u^- + u^+) . n^-.
+ *
+ * Coefficient layout ("state"): [n_elem][dim][n_basis] row-major, element-major.  Component
+ * i of element T is sum_m c[T][i][m] phi_m(F_T^-1 x) with phi_m the orthonormal Dubiner basis
+ * on the unit reference simplex (order: total degree ascending, then the last index
+ * descending, then the middle one) and F_T(xi) = v_0 + [v_1-v_0, ..., v_d-v_0] xi from the
+ * element's vertex order as given, which the library never changes.
+ *
+ * Conventions for every call:
+ *   - Return value: dg_status, 0 on success, negative on error; dg_last_error() gives a
+ *     message for the calling thread.  No C++ exception crosses this boundary.
+ *   - "dev" pointers are device memory on the current HIP device, 16-byte aligned, owned by
+ *     the caller; "host" pointers are host memory owned by the caller.
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).  Compute calls are
+ *     asynchronous on that stream unless stated.
+ *   - Input, output and work buffers of one call must not overlap unless stated.
+ */
+#ifndef DGCONV_H
+#define DGCONV_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DG_OK = 0,
+  DG_EINVAL = -1,       /* bad argument: null/misaligned pointer, size, k, dim, dt, n */
+  DG_ENOMEM = -2,       /* device or host allocation failed */
+  DG_EDEVICE = -3,      /* a HIP runtime call failed */
+  DG_EUNSUPPORTED = -4, /* valid request this build does not implement (e.g. k too large) */
+  DG_ENONFINITE = -5,   /* non-finite values detected */
+  DG_EMESH = -6         /* degenerate element, unmatched or non-manifold facet */
+} dg_status;
+
+/* Arithmetic of the operator.  The state is FP64 except for DG_FP32 (FP32 state). */
+typedef enum {
+  DG_FP64 = 0,      /* everything in FP64 */
+  DG_FP32 = 1,      /* FP32 state and arithmetic */
+  DG_MIX_BF16x3 = 4,/* FP64 state, facet fluxes and RK; basis contractions as 3-way split
+                       BF16 products on the matrix cores with FP32 accumulation */
+  DG_MIX_F16x2 = 5  /* as above with 2-way split FP16 products (per-element power-of-two
+                       scaling) */
+} dg_precision;
+
+typedef struct dg_mesh dg_mesh; /* opaque; immutable after creation */
+
+typedef struct {
+  int dim, k, n_basis;      /* n_basis = C(k+dim, dim) per component */
+  int64_t n_elem, n_facet;  /* n_facet = n_elem (dim+1) / 2 */
+  int64_t n_dof;            /* n_elem * dim * n_basis */
+  int nq_vol, nq_facet;     /* quadrature points per element volume / per facet */
+  int n_types, n_tiles;     /* element classes with identical facet tables; 64-wide tiles */
+  double h_min;             /* smallest facet measure (2D) or its square root (3D) */
+  double volume;            /* sum of element volumes */
+} dg_mesh_info;
+
+/* Create a periodic mesh of affine simplices (synchronous, host only).  The device tables
+ * are uploaded to the current HIP device by the first compute call (dg_convection_apply,
+ * dg_rk_substeps, dg_reduce), synchronously; later compute calls must run with the same
+ * device current.  xyz: host [n_vert][dim]; elem: host [n_elem][dim+1] vertex ids, local
+ * order = element frame; period: host [dim] box lengths (required: every facet must be
+ * matched by a facet of another element, modulo the period).  Facets are matched by centroid
+ * modulo the period.  k: 0..6 in 2D, 0..4 in 3D.
+ * Errors: DG_EINVAL (dim not 2/3, k out of range, null pointers, vertex id out of range),
+ * DG_EMESH (|det J| <= 1e-12 h^dim, unmatched or non-manifold facet),
+ * DG_ENOMEM, DG_EDEVICE.  *out is set only on success; free with dg_mesh_destroy. */
+dg_status dg_mesh_create(int dim, int k, int64_t n_vert, const double* xyz, int64_t n_elem,
+                         const int64_t* elem, const double* period, dg_mesh** out);
+
+/* Periodic unit box, n^dim squares split into 2 triangles or cubes split into 6 tetrahedra
+ * (synchronous).  2D: square (i,j) -> lower (v00,v10,v11) id 2(jn+i), upper (v11,v01,v00)
+ * id 2(jn+i)+1.  3D: cube (i,j,l), index (ln+j)n+i, Kuhn split along v000->v111: tet s =
+ * (v000, v000+e_s0, v000+e_s0+e_s1, v111) for the permutations s of (x,y,z) in lexicographic
+ * order, id 6*cube+index(s).  n >= 1. */
+dg_status dg_mesh_create_box(int dim, int n, int k, dg_mesh** out);
+
+void dg_mesh_destroy(dg_mesh* mesh); /* NULL is a no-op; synchronises the device */
+
+dg_status dg_mesh_get_info(const dg_mesh* mesh, dg_mesh_info* out);
+
+/* Unwrapped vertex coordinates of every element, host [n_elem][dim+1][dim] (synchronous). */
+dg_status dg_mesh_get_vertices(const dg_mesh* mesh, double* xyz_out);
+
+/* Facet connectivity, host [n_elem][dim+1] each: neighbour element across local facet f
+ * (the facet opposite local vertex f) and that facet's local index in the neighbour. */
+dg_status dg_mesh_get_neighbors(const dg_mesh* mesh, int32_t* nbr_out, int32_t* nbr_facet_out);
+
+/* L2 projection onto the DG space (synchronous, host).  dg_project_points writes the
+ * physical points of a collapsed Gauss rule with n points per direction (n in 1..32),
+ * host [n_elem][n^dim][dim]; dg_project takes a field sampled there, host
+ * [n_elem][n^dim][dim], and writes the coefficients, host [n_elem][dim][n_basis]. */
+dg_status dg_project_points(const dg_mesh* mesh, int n, double* xyz_out);
+dg_status dg_project(const dg_mesh* mesh, int n, const double* vals, double* coef_out);
+
+/* r = -(M^V)^-1 C^V(u) w  (one operator application).
+ * w: dev state; u: dev state (frozen convecting velocity) or NULL for u := w (the nonlinear
+ * self-convection div(w (x) w)); r: dev state, output.  State element type is double except
+ * for DG_FP32 (float).  r must not overlap w or u. */
+dg_status dg_convection_apply(const dg_mesh* mesh, dg_precision prec, const void* w,
+                              const void* u, void* r, void* stream);
+
+/* n substeps of three-stage SSP-RK3 (Shu-Osher) with step dt for ds w = r(w), in place:
+ *   w1 = w + dt r(w);  w2 = 3/4 w + 1/4 (w1 + dt r(w1));  w <- 1/3 w + 2/3 (w2 + dt r(w2)).
+ * u: NULL (self-convection, re-evaluated at every stage) or a dev state (frozen velocity).
+ * work: dev, at least 2 states, or NULL to use a buffer owned by the mesh (then concurrent
+ * calls on one mesh must be serialised by the caller).  dt > 0 finite, n >= 0. */
+dg_status dg_rk_substeps(const dg_mesh* mesh, dg_precision prec, void* w, double dt, int n,
+                         const void* u, void* work, void* stream);
+
+/* Reductions of FP64 states into out_dev (dev, doubles), deterministic:
+ *   DG_RED_MAXVEL   out[0] = max over the volume quadrature points of |a(x)|
+ *   DG_RED_ENERGY   out[0] = 1/2 int |a|^2 dx
+ *   DG_RED_MOMENTUM out[0..dim-1] = int a dx
+ *   DG_RED_L2DIFF   out[0] = ||a - b||_L2, out[1] = ||b||_L2
+ *   DG_RED_NONFINITE out[0] = number of non-finite coefficients of a */
+enum { DG_RED_MAXVEL = 0, DG_RED_ENERGY = 1, DG_RED_MOMENTUM = 2, DG_RED_L2DIFF = 3,
+       DG_RED_NONFINITE = 4 };
+dg_status dg_reduce(const dg_mesh* mesh, int what, const double* a, const double* b,
+                    double* out_dev, void* stream);
+
+/* The library's reference basis on the unit simplex (host): vals [n_pts][n_basis] and,
+ * if grads is not NULL, reference gradients [n_pts][n_basis][dim] at pts [n_pts][dim]. */
+dg_status dg_eval_basis(int dim, int k, int64_t n_pts, const double* pts, double* vals,
+                        double* grads);
+
+const char* dg_last_error(void);
+const char* dg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGCONV_H */

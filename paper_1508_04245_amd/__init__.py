@@ -1,1 +1,194 @@
-"""MI355X-native upwind-DG convection (binding to the HIP library; filled in below)."""
+"""Python binding of libdgconv.so, the MI355X upwind-DG convection library.
+
+Argument marshalling only: every step of the operator and the Runge-Kutta substeps runs in the
+library's HIP kernels.  PyTorch provides device memory and streams.  The library must be built
+(``python -m paper_1508_04245_amd.build``); without it every call raises.
+
+Names follow include/dgconv.h.  States are torch tensors of shape [n_elem, dim, n_basis],
+contiguous, on the current CUDA(HIP) device, float64 (float32 for precision "fp32").
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdgconv.so")
+
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 4, "f16x2": 5}
+RED = {"maxvel": 0, "energy": 1, "momentum": 2, "l2diff": 3, "nonfinite": 4}
+
+_lib = None
+
+
+class DGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("dgconv error %d: %s" % (status, msg))
+        self.status = status
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("k", ctypes.c_int), ("n_basis", ctypes.c_int),
+                ("n_elem", ctypes.c_int64), ("n_facet", ctypes.c_int64),
+                ("n_dof", ctypes.c_int64), ("nq_vol", ctypes.c_int), ("nq_facet", ctypes.c_int),
+                ("n_types", ctypes.c_int), ("n_tiles", ctypes.c_int),
+                ("h_min", ctypes.c_double), ("volume", ctypes.c_double)]
+
+
+def lib():
+    """Load libdgconv.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libdgconv.so is not built; run: python -m paper_1508_04245_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "dg_mesh_create": [I, I, I64, P, I64, P, P, P],
+        "dg_mesh_create_box": [I, I, I, P],
+        "dg_mesh_destroy": [P],
+        "dg_mesh_get_info": [P, P],
+        "dg_mesh_get_vertices": [P, P],
+        "dg_mesh_get_neighbors": [P, P, P],
+        "dg_project_points": [P, I, P],
+        "dg_project": [P, I, P, P],
+        "dg_convection_apply": [P, I, P, P, P, P],
+        "dg_rk_substeps": [P, I, P, D, I, P, P, P],
+        "dg_reduce": [P, I, P, P, P, P],
+        "dg_eval_basis": [I, I, I64, P, P, P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = None if name == "dg_mesh_destroy" else ctypes.c_int
+    L.dg_last_error.restype = ctypes.c_char_p
+    L.dg_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != 0:
+        raise DGError(status, lib().dg_last_error().decode())
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else ctypes.c_void_p(a)
+
+
+def _dev(t, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("expected dtype %s, got %s" % (dtype, t.dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def eval_basis(dim, k, pts):
+    """The library's reference basis and gradients at pts [n, dim] (host)."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    n = pts.shape[0]
+    npb = {2: (k + 1) * (k + 2) // 2, 3: (k + 1) * (k + 2) * (k + 3) // 6}[dim]
+    vals = np.zeros((n, npb))
+    grads = np.zeros((n, npb, dim))
+    _check(lib().dg_eval_basis(dim, k, n, _ptr(pts), _ptr(vals), _ptr(grads)))
+    return vals, grads
+
+
+class Mesh:
+    """A periodic affine simplicial mesh with degree-k vector DG space (dg_mesh)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        info = _Info()
+        _check(lib().dg_mesh_get_info(self._h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in _Info._fields_}
+        self.dim, self.k, self.np = info.dim, info.k, info.n_basis
+        self.E = info.n_elem
+
+    @classmethod
+    def box(cls, dim, n, k):
+        h = ctypes.c_void_p()
+        _check(lib().dg_mesh_create_box(dim, n, k, ctypes.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def from_arrays(cls, dim, k, xyz, elem, period):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        elem = np.ascontiguousarray(elem, dtype=np.int64)
+        period = np.ascontiguousarray(period, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(lib().dg_mesh_create(dim, k, xyz.shape[0], _ptr(xyz), elem.shape[0], _ptr(elem),
+                                    _ptr(period), ctypes.byref(h)))
+        return cls(h)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.dg_mesh_destroy(self._h)
+            self._h = None
+
+    @property
+    def shape(self):
+        return (self.E, self.dim, self.np)
+
+    def vertices(self):
+        out = np.zeros((self.E, self.dim + 1, self.dim))
+        _check(lib().dg_mesh_get_vertices(self._h, _ptr(out)))
+        return out
+
+    def neighbors(self):
+        nb = np.zeros((self.E, self.dim + 1), dtype=np.int32)
+        nf = np.zeros((self.E, self.dim + 1), dtype=np.int32)
+        _check(lib().dg_mesh_get_neighbors(self._h, _ptr(nb), _ptr(nf)))
+        return nb, nf
+
+    def project_points(self, n):
+        out = np.zeros((self.E, n ** self.dim, self.dim))
+        _check(lib().dg_project_points(self._h, n, _ptr(out)))
+        return out
+
+    def project(self, vals, n):
+        vals = np.ascontiguousarray(vals, dtype=np.float64)
+        out = np.zeros(self.shape)
+        _check(lib().dg_project(self._h, n, _ptr(vals), _ptr(out)))
+        return out
+
+    # ---- device calls
+    def apply(self, w, u=None, out=None, precision="fp64", stream=None):
+        """r = -(M^V)^-1 C^V(u) w on the device (u=None: self-convection)."""
+        import torch
+        dt = torch.float32 if precision == "fp32" else torch.float64
+        if out is None:
+            out = torch.empty_like(w)
+        _check(lib().dg_convection_apply(self._h, PREC[precision], _dev(w, dt),
+                                         None if u is None else _dev(u, dt), _dev(out, dt),
+                                         _stream(stream)))
+        return out
+
+    def rk_substeps(self, w, dt, n, u=None, work=None, precision="fp64", stream=None):
+        """n SSP-RK3 substeps in place on w."""
+        import torch
+        ty = torch.float32 if precision == "fp32" else torch.float64
+        _check(lib().dg_rk_substeps(self._h, PREC[precision], _dev(w, ty), float(dt), int(n),
+                                    None if u is None else _dev(u, ty),
+                                    None if work is None else _dev(work, ty), _stream(stream)))
+        return w
+
+    def reduce(self, what, a, b=None, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.zeros(4, dtype=torch.float64, device=a.device)
+        _check(lib().dg_reduce(self._h, RED[what], _dev(a, torch.float64),
+                               None if b is None else _dev(b, torch.float64),
+                               _dev(out, torch.float64), _stream(stream)))
+        return out

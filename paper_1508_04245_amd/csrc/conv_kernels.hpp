@@ -1,0 +1,251 @@
+// CDNA4 (gfx950) kernels of the upwind-DG convection operator, plain FP64 / FP32 path.
+//
+// One lane per element, one wavefront per 64-element tile of a single element class
+// (identical facet tables), so every table entry a lane needs is wave-uniform: tables are
+// read through constant-address-space pointers with uniform offsets and arrive in SGPRs
+// (scalar loads), and each multiply-add of a basis contraction is a VALU FMA with one scalar
+// operand.  The per-element state, the neighbour states and the accumulators stay in VGPRs.
+//
+// Per element and application (Sec. 2.3 upwind form, Sec. 2.4 discrete operator, inverse of
+// the diagonal mass matrix folded in):
+//   volume:  R[i][m] += sum_q w_i(x_q) (uh(x_q) . w_q grad^ phi_m(x_q)),  uh = J^-1 u
+//   facets:  R[i][m] -= sum_f sum_q w^F_q phi_m(x_q) [ b {w_i} + |b|/2 [w_i] ],
+//            b = 1/2 (u^- + u^+) . (J^-T n^_f |F^_f|)   (= beta |F| / |det J|)
+//   r = R   (the orthonormal reference basis makes M_T = |det J| I, which cancels)
+// and, in the fused Runge-Kutta mode, out = a w0 + b (x + dt r) for the stage of SSP-RK3.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace dgk {
+
+template <int D, int K>
+struct Shape {
+  static constexpr int NP = D == 2 ? (K + 1) * (K + 2) / 2 : (K + 1) * (K + 2) * (K + 3) / 6;
+  static constexpr int NV1 = (3 * K + 1) / 2 < 1 ? 1 : (3 * K + 1) / 2;  // exact to 3k-1
+  static constexpr int NQ = D == 2 ? NV1 * NV1 : NV1 * NV1 * NV1;
+  static constexpr int NF1 = (3 * K + 2) / 2 < 1 ? 1 : (3 * K + 2) / 2;  // exact to 3k
+  static constexpr int NFQ = D == 2 ? NF1 : NF1 * NF1;
+  static constexpr int NPERM = D == 2 ? 2 : 6;
+  static constexpr int NTAB = (D + 1) * NPERM;
+  static constexpr int OFF_BV = 0;
+  static constexpr int OFF_DV = NQ * NP;
+  static constexpr int OFF_TR = OFF_DV + NQ * NP * D;
+  static constexpr int OFF_LF = OFF_TR + NTAB * NFQ * NP;
+  static constexpr int TOTAL = OFF_LF + NTAB * NFQ * NP;
+};
+
+template <typename T>
+struct ConvArgs {
+  const T* x;          // state the operator acts on (neighbour traces are read from it)
+  const T* u;          // frozen convecting velocity, or nullptr (u := x)
+  const T* w0;         // Runge-Kutta base state (mode 1, a != 0)
+  T* out;              // mode 0: r;  mode 1: a w0 + b (x + dt r)
+  const T* tab;        // reference tables (Shape offsets)
+  const T* jinv;       // [E][D][D]
+  const int* nbr;      // [E][D+1]
+  const int* elem_list;// [ntiles*64], -1 padded
+  const int* tile_type;// [ntiles]
+  const int* type_tab; // [ntypes][D+1]: own table | nbr table << 16
+  int ntiles;
+  int mode;
+  T a, b, dt;
+};
+
+// scaled outward reference normal n^_f |F^_f| of local facet f (opposite vertex f)
+template <int D, typename T>
+__device__ __forceinline__ T nref(int f, int j) {
+  if (f == 0) return D == 2 ? T(1) : T(0.5);
+  return j == f - 1 ? (D == 2 ? T(-1) : T(-0.5)) : T(0);
+}
+
+template <int D, int K, typename T, bool SELF>
+__global__ void __launch_bounds__(256) conv_kernel(ConvArgs<T> A) {
+  using S = Shape<D, K>;
+  constexpr int NP = S::NP;
+  typedef const T __attribute__((address_space(4)))* cptr;
+  typedef const int __attribute__((address_space(4)))* ciptr;
+  const int lane = threadIdx.x & 63;
+  const int tile = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (tile >= A.ntiles) return;
+  const int e_raw = A.elem_list[tile * 64 + lane];
+  const int e = e_raw >= 0 ? e_raw : A.elem_list[tile * 64];  // padded lanes redo lane 0
+  const int type = __builtin_amdgcn_readfirstlane(A.tile_type[tile]);
+  const cptr tab = (cptr)A.tab;
+  const ciptr ttab = (ciptr)A.type_tab;
+
+  T c[D][NP], uc[SELF ? 1 : D][SELF ? 1 : NP], R[D][NP], ji[D][D];
+  {
+    const T* __restrict__ p = A.x + (size_t)e * D * NP;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int m = 0; m < NP; ++m) c[i][m] = p[i * NP + m];
+    if constexpr (!SELF) {
+      const T* __restrict__ pu = A.u + (size_t)e * D * NP;
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int m = 0; m < NP; ++m) uc[i][m] = pu[i * NP + m];
+    }
+    const T* __restrict__ pj = A.jinv + (size_t)e * D * D;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) ji[i][j] = pj[i * D + j];
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int m = 0; m < NP; ++m) R[i][m] = T(0);
+
+  // ---- volume term
+#pragma unroll 1
+  for (int q = 0; q < S::NQ; ++q) {
+    const cptr bq = tab + S::OFF_BV + q * NP;
+    const cptr dq = tab + S::OFF_DV + q * NP * D;
+    T wq[D], uq[D], uh[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) wq[i] = T(0);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      const T bm = bq[m];
+#pragma unroll
+      for (int i = 0; i < D; ++i) wq[i] = fma(bm, c[i][m], wq[i]);
+    }
+    if constexpr (SELF) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) uq[i] = wq[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; ++i) uq[i] = T(0);
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        const T bm = bq[m];
+#pragma unroll
+        for (int i = 0; i < D; ++i) uq[i] = fma(bm, uc[i][m], uq[i]);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      T s = T(0);
+#pragma unroll
+      for (int j = 0; j < D; ++j) s = fma(ji[a][j], uq[j], s);
+      uh[a] = s;
+    }
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      T P = T(0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) P = fma(uh[a], dq[m * D + a], P);
+#pragma unroll
+      for (int i = 0; i < D; ++i) R[i][m] = fma(wq[i], P, R[i][m]);
+    }
+  }
+
+  // ---- facet terms (pointwise upwind flux)
+#pragma unroll
+  for (int f = 0; f <= D; ++f) {
+    const int tt = ttab[type * (D + 1) + f];
+    const int own = __builtin_amdgcn_readfirstlane(tt & 0xffff);
+    const int nbt = __builtin_amdgcn_readfirstlane(tt >> 16);
+    const cptr tro = tab + S::OFF_TR + own * S::NFQ * NP;
+    const cptr trn = tab + S::OFF_TR + nbt * S::NFQ * NP;
+    const cptr lfo = tab + S::OFF_LF + own * S::NFQ * NP;
+    const int ne = A.nbr[(size_t)e * (D + 1) + f];
+    T cn[D][NP], un[SELF ? 1 : D][SELF ? 1 : NP];
+    {
+      const T* __restrict__ p = A.x + (size_t)ne * D * NP;
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int m = 0; m < NP; ++m) cn[i][m] = p[i * NP + m];
+      if constexpr (!SELF) {
+        const T* __restrict__ pu = A.u + (size_t)ne * D * NP;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int m = 0; m < NP; ++m) un[i][m] = pu[i * NP + m];
+      }
+    }
+    T Nt[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T s = T(0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) s = fma(ji[a][j], nref<D, T>(f, a), s);
+      Nt[j] = s;
+    }
+#pragma unroll 1
+    for (int q = 0; q < S::NFQ; ++q) {
+      T wm[D], wp[D], um[D], up[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) { wm[i] = T(0); wp[i] = T(0); }
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        const T to = tro[q * NP + m], tn = trn[q * NP + m];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          wm[i] = fma(to, c[i][m], wm[i]);
+          wp[i] = fma(tn, cn[i][m], wp[i]);
+        }
+      }
+      if constexpr (SELF) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) { um[i] = wm[i]; up[i] = wp[i]; }
+      } else {
+#pragma unroll
+        for (int i = 0; i < D; ++i) { um[i] = T(0); up[i] = T(0); }
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+          const T to = tro[q * NP + m], tn = trn[q * NP + m];
+#pragma unroll
+          for (int i = 0; i < D; ++i) {
+            um[i] = fma(to, uc[i][m], um[i]);
+            up[i] = fma(tn, un[i][m], up[i]);
+          }
+        }
+      }
+      T bb = T(0);
+#pragma unroll
+      for (int j = 0; j < D; ++j) bb = fma(um[j] + up[j], Nt[j], bb);
+      // b = bb / 2;  F = b (wm + wp) / 2 + |b| (wm - wp) / 2
+      const T hb = T(0.25) * bb;
+      const T ha = T(0.25) * fabs(bb);
+      T F[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) F[i] = hb * (wm[i] + wp[i]) + ha * (wm[i] - wp[i]);
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        const T l = lfo[q * NP + m];
+#pragma unroll
+        for (int i = 0; i < D; ++i) R[i][m] = fma(-l, F[i], R[i][m]);
+      }
+    }
+  }
+
+  if (e_raw < 0) return;
+  T* __restrict__ o = A.out + (size_t)e * D * NP;
+  if (A.mode == 0) {
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int m = 0; m < NP; ++m) o[i * NP + m] = R[i][m];
+  } else {
+    const T a = A.a, b = A.b, dt = A.dt;
+    if (a != T(0)) {
+      const T* __restrict__ pw = A.w0 + (size_t)e * D * NP;
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int m = 0; m < NP; ++m)
+          o[i * NP + m] = fma(a, pw[i * NP + m], b * fma(dt, R[i][m], c[i][m]));
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int m = 0; m < NP; ++m) o[i * NP + m] = b * fma(dt, R[i][m], c[i][m]);
+    }
+  }
+}
+
+}  // namespace dgk

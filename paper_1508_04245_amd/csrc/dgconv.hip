@@ -1,0 +1,514 @@
+// C ABI of the upwind-DG convection library (see include/dgconv.h): mesh creation and
+// device tables, operator application, fused SSP-RK3 substeps, reductions.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/dgconv.h"
+#include "conv_kernels.hpp"
+#include "mesh.hpp"
+#include "refelem.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+dg_status fail(dg_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? DG_ENOMEM : DG_EDEVICE,                   \
+                  std::string(#expr ": ") + hipGetErrorString(e_));                     \
+  } while (0)
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+constexpr int kMaxK2 = 6, kMaxK3 = 4;
+constexpr int kRedBlock = 256;
+
+}  // namespace
+
+struct dg_mesh {
+  dgmesh::Host h;
+  dgmesh::Tables t;
+  int device = 0;
+  double* d_tab = nullptr;
+  float* d_tab_f = nullptr;
+  double* d_jinv = nullptr;
+  float* d_jinv_f = nullptr;
+  double* d_absdet = nullptr;
+  int* d_nbr = nullptr;
+  int* d_elem_list = nullptr;
+  int* d_tile_type = nullptr;
+  int* d_type_tab = nullptr;
+  mutable void* d_work = nullptr;
+  mutable size_t work_bytes = 0;
+  double* d_partial = nullptr;  // reduction partials
+  int n_partial = 0;
+  bool on_device = false;
+  std::mutex mu;
+};
+
+namespace {
+
+// ------------------------------------------------------------------ reductions
+// what: 1 energy, 2 momentum (first dim outputs), 3 l2diff (2 outputs), 4 nonfinite
+__global__ void __launch_bounds__(kRedBlock)
+elem_reduce_kernel(int what, int dim, int np, int64_t E, const double* __restrict__ a,
+                   const double* __restrict__ b, const double* __restrict__ absdet,
+                   double phi0_vol, double* __restrict__ partial) {
+  __shared__ double sh[kRedBlock][3];
+  const int64_t t = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  double v[3] = {0, 0, 0};
+  if (t < E) {
+    const double* pa = a + t * dim * np;
+    const double J = absdet[t];
+    if (what == 1) {
+      double s = 0;
+      for (int i = 0; i < dim * np; ++i) s = fma(pa[i], pa[i], s);
+      v[0] = 0.5 * J * s;
+    } else if (what == 2) {
+      for (int i = 0; i < dim; ++i) v[i] = J * pa[i * np] * phi0_vol;
+    } else if (what == 3) {
+      const double* pb = b + t * dim * np;
+      double s0 = 0, s1 = 0;
+      for (int i = 0; i < dim * np; ++i) {
+        const double d = pa[i] - pb[i];
+        s0 = fma(d, d, s0);
+        s1 = fma(pb[i], pb[i], s1);
+      }
+      v[0] = J * s0;
+      v[1] = J * s1;
+    } else {
+      double s = 0;
+      for (int i = 0; i < dim * np; ++i) s += isfinite(pa[i]) ? 0.0 : 1.0;
+      v[0] = s;
+    }
+  }
+  for (int c = 0; c < 3; ++c) sh[threadIdx.x][c] = v[c];
+  __syncthreads();
+  for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int c = 0; c < 3; ++c) sh[threadIdx.x][c] += sh[threadIdx.x + s][c];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 3; ++c) partial[blockIdx.x * 3 + c] = sh[0][c];
+}
+
+// max over the volume points of |w|, per block
+template <int D, int K>
+__global__ void __launch_bounds__(kRedBlock)
+maxvel_kernel(int64_t E, const double* __restrict__ a, const double* __restrict__ tab,
+              double* __restrict__ partial) {
+  using S = dgk::Shape<D, K>;
+  __shared__ double sh[kRedBlock];
+  const int64_t t = (int64_t)blockIdx.x * kRedBlock + threadIdx.x;
+  double mx = 0;
+  if (t < E) {
+    const double* pa = a + t * D * S::NP;
+    for (int q = 0; q < S::NQ; ++q) {
+      double s = 0;
+      for (int i = 0; i < D; ++i) {
+        double w = 0;
+        for (int m = 0; m < S::NP; ++m) w = fma(tab[S::OFF_BV + q * S::NP + m], pa[i * S::NP + m], w);
+        s = fma(w, w, s);
+      }
+      mx = fmax(mx, s);
+    }
+  }
+  sh[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x * 3] = sqrt(sh[0]);
+    partial[blockIdx.x * 3 + 1] = 0;
+    partial[blockIdx.x * 3 + 2] = 0;
+  }
+}
+
+// single block: combine the partials in a fixed order
+__global__ void __launch_bounds__(kRedBlock)
+final_reduce_kernel(int nblocks, int is_max, int nout, int sqrt_out,
+                    const double* __restrict__ partial, double* __restrict__ out) {
+  __shared__ double sh[kRedBlock][3];
+  double v[3] = {0, 0, 0};
+  for (int b = threadIdx.x; b < nblocks; b += kRedBlock)
+    for (int c = 0; c < 3; ++c)
+      v[c] = is_max ? fmax(v[c], partial[b * 3 + c]) : v[c] + partial[b * 3 + c];
+  for (int c = 0; c < 3; ++c) sh[threadIdx.x][c] = v[c];
+  __syncthreads();
+  for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int c = 0; c < 3; ++c)
+        sh[threadIdx.x][c] = is_max ? fmax(sh[threadIdx.x][c], sh[threadIdx.x + s][c])
+                                    : sh[threadIdx.x][c] + sh[threadIdx.x + s][c];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int c = 0; c < nout; ++c) out[c] = sqrt_out ? sqrt(sh[0][c]) : sh[0][c];
+}
+
+// ------------------------------------------------------------------ dispatch
+template <int D, int K>
+hipError_t launch_maxvel(const dg_mesh* m, const double* a, hipStream_t s) {
+  const int nb = (int)((m->h.E + kRedBlock - 1) / kRedBlock);
+  hipLaunchKernelGGL((maxvel_kernel<D, K>), dim3(nb), dim3(kRedBlock), 0, s, m->h.E, a,
+                     m->d_tab, m->d_partial);
+  return hipGetLastError();
+}
+
+template <int D, int K, typename T, bool SELF>
+hipError_t launch_conv_dk(const dg_mesh* m, const dgk::ConvArgs<T>& a, hipStream_t s) {
+  // the kernel's compile-time table layout must match the host tables it reads
+  if ((size_t)dgk::Shape<D, K>::TOTAL != m->t.total || dgk::Shape<D, K>::NP != m->h.np)
+    return hipErrorInvalidValue;
+  if ((int64_t)m->h.elem_list.size() != (int64_t)m->h.ntiles * 64) return hipErrorInvalidValue;
+  const dim3 grid((m->h.ntiles + 3) / 4), block(256);
+  hipLaunchKernelGGL((dgk::conv_kernel<D, K, T, SELF>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, bool SELF>
+hipError_t launch_conv(const dg_mesh* m, const dgk::ConvArgs<T>& a, hipStream_t s) {
+  const int d = m->h.dim, k = m->h.k;
+#define DG_CASE(D_, K_) \
+  if (d == D_ && k == K_) return launch_conv_dk<D_, K_, T, SELF>(m, a, s);
+  DG_CASE(2, 0) DG_CASE(2, 1) DG_CASE(2, 2) DG_CASE(2, 3) DG_CASE(2, 4) DG_CASE(2, 5)
+  DG_CASE(2, 6) DG_CASE(3, 0) DG_CASE(3, 1) DG_CASE(3, 2) DG_CASE(3, 3) DG_CASE(3, 4)
+#undef DG_CASE
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_conv_any(const dg_mesh* m, const dgk::ConvArgs<T>& a, hipStream_t s) {
+  return a.u ? launch_conv<T, false>(m, a, s) : launch_conv<T, true>(m, a, s);
+}
+
+template <typename T>
+dgk::ConvArgs<T> base_args(const dg_mesh* m) {
+  dgk::ConvArgs<T> a{};
+  if constexpr (sizeof(T) == 8) {
+    a.tab = m->d_tab;
+    a.jinv = m->d_jinv;
+  } else {
+    a.tab = m->d_tab_f;
+    a.jinv = m->d_jinv_f;
+  }
+  a.nbr = m->d_nbr;
+  a.elem_list = m->d_elem_list;
+  a.tile_type = m->d_tile_type;
+  a.type_tab = m->d_type_tab;
+  a.ntiles = m->h.ntiles;
+  return a;
+}
+
+template <typename T>
+dg_status run_apply(const dg_mesh* m, const void* w, const void* u, void* r, hipStream_t s) {
+  auto a = base_args<T>(m);
+  a.x = (const T*)w;
+  a.u = (const T*)u;
+  a.out = (T*)r;
+  a.mode = 0;
+  HIP_TRY(launch_conv_any<T>(m, a, s));
+  return DG_OK;
+}
+
+template <typename T>
+dg_status run_rk(const dg_mesh* m, void* w, double dt, int n, const void* u, void* work,
+                 hipStream_t s) {
+  const size_t n_state = (size_t)m->h.E * m->h.dim * m->h.np;
+  T* w0 = (T*)w;
+  T* w1 = (T*)work;
+  T* w2 = w1 + n_state;
+  auto a = base_args<T>(m);
+  a.u = (const T*)u;
+  a.mode = 1;
+  a.dt = (T)dt;
+  for (int it = 0; it < n; ++it) {
+    a.x = w0; a.w0 = nullptr; a.out = w1; a.a = T(0); a.b = T(1);
+    HIP_TRY(launch_conv_any<T>(m, a, s));
+    a.x = w1; a.w0 = w0; a.out = w2; a.a = T(0.75); a.b = T(0.25);
+    HIP_TRY(launch_conv_any<T>(m, a, s));
+    a.x = w2; a.w0 = w0; a.out = w0; a.a = T(1.0 / 3.0); a.b = T(2.0 / 3.0);
+    HIP_TRY(launch_conv_any<T>(m, a, s));
+  }
+  return DG_OK;
+}
+
+dg_status check_k(int dim, int k) {
+  if (dim != 2 && dim != 3) return fail(DG_EINVAL, "dim must be 2 or 3");
+  if (k < 0) return fail(DG_EINVAL, "k must be >= 0");
+  if ((dim == 2 && k > kMaxK2) || (dim == 3 && k > kMaxK3))
+    return fail(DG_EUNSUPPORTED, "k above the compiled range (2D: 0..6, 3D: 0..4)");
+  return DG_OK;
+}
+
+template <typename T>
+dg_status upload(const std::vector<T>& v, T** d) {
+  HIP_TRY(hipMalloc((void**)d, v.size() * sizeof(T) + 16));
+  HIP_TRY(hipMemcpy(*d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return DG_OK;
+}
+
+// Device tables are uploaded on the first compute call (synchronously), to the device that
+// is current then; later calls must use the same device.
+dg_status ensure_device(const dg_mesh* cm) {
+  dg_mesh* m = const_cast<dg_mesh*>(cm);
+  std::lock_guard<std::mutex> lock(m->mu);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (m->on_device) {
+    if (dev != m->device) return fail(DG_EINVAL, "mesh was uploaded to another device");
+    return DG_OK;
+  }
+  m->device = dev;
+  std::vector<float> tabf(m->t.data.begin(), m->t.data.end());
+  std::vector<float> jinvf(m->h.jinv.begin(), m->h.jinv.end());
+  std::vector<double> zeros((size_t)m->n_partial * 3, 0.0);
+  dg_status s = DG_OK;
+  if ((s = upload(m->t.data, &m->d_tab)) != DG_OK || (s = upload(tabf, &m->d_tab_f)) != DG_OK ||
+      (s = upload(m->h.jinv, &m->d_jinv)) != DG_OK || (s = upload(jinvf, &m->d_jinv_f)) != DG_OK ||
+      (s = upload(m->h.absdet, &m->d_absdet)) != DG_OK ||
+      (s = upload(m->h.nbr, &m->d_nbr)) != DG_OK ||
+      (s = upload(m->h.elem_list, &m->d_elem_list)) != DG_OK ||
+      (s = upload(m->h.tile_type, &m->d_tile_type)) != DG_OK ||
+      (s = upload(m->h.type_tab, &m->d_type_tab)) != DG_OK ||
+      (s = upload(zeros, &m->d_partial)) != DG_OK)
+    return s;
+  m->on_device = true;
+  return DG_OK;
+}
+
+void free_mesh(dg_mesh* m) {
+  if (!m) return;
+  void* ptrs[] = {m->d_tab, m->d_tab_f, m->d_jinv, m->d_jinv_f, m->d_absdet, m->d_nbr,
+                  m->d_elem_list, m->d_tile_type, m->d_type_tab, m->d_work, m->d_partial};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete m;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dg_last_error(void) { return g_err.c_str(); }
+const char* dg_version(void) { return "dgconv 0.1 gfx950"; }
+
+dg_status dg_mesh_create(int dim, int k, int64_t n_vert, const double* xyz, int64_t n_elem,
+                         const int64_t* elem, const double* period, dg_mesh** out) {
+  if (!out) return fail(DG_EINVAL, "out is NULL");
+  dg_status st = check_k(dim, k);
+  if (st != DG_OK) return st;
+  if (!xyz || !elem || !period || n_vert <= 0 || n_elem <= 0)
+    return fail(DG_EINVAL, "null pointer or empty mesh");
+  if (n_elem > (int64_t)0x7fffffff / 64) return fail(DG_EINVAL, "too many elements");
+  dg_mesh* m = new (std::nothrow) dg_mesh();
+  if (!m) return fail(DG_ENOMEM, "host allocation");
+  std::string err;
+  const int rc = dgmesh::build(dim, k, n_vert, xyz, n_elem, elem, period, m->h, err);
+  if (rc != 0) {
+    delete m;
+    return fail(rc == -6 ? DG_EMESH : DG_EINVAL, err);
+  }
+  dgmesh::build_tables(dim, k, m->t);
+  m->n_partial = (int)((n_elem + kRedBlock - 1) / kRedBlock);
+  *out = m;
+  return DG_OK;
+}
+
+dg_status dg_mesh_create_box(int dim, int n, int k, dg_mesh** out) {
+  if (dim != 2 && dim != 3) return fail(DG_EINVAL, "dim must be 2 or 3");
+  if (n < 1 || n > 4096) return fail(DG_EINVAL, "n out of range");
+  std::vector<double> xyz;
+  std::vector<int64_t> elem;
+  dgmesh::box_connectivity(dim, n, xyz, elem);
+  const double period[3] = {1.0, 1.0, 1.0};
+  return dg_mesh_create(dim, k, (int64_t)(xyz.size() / dim), xyz.data(),
+                        (int64_t)(elem.size() / (dim + 1)), elem.data(), period, out);
+}
+
+void dg_mesh_destroy(dg_mesh* mesh) {
+  if (!mesh) return;
+  if (mesh->on_device) (void)hipDeviceSynchronize();
+  free_mesh(mesh);
+}
+
+dg_status dg_eval_basis(int dim, int k, int64_t n_pts, const double* pts, double* vals,
+                        double* grads) {
+  dg_status st = check_k(dim, k);
+  if (st != DG_OK) return st;
+  if (n_pts < 0 || (n_pts > 0 && (!pts || !vals))) return fail(DG_EINVAL, "null pointer");
+  const int np = dgref::n_basis(dim, k);
+  for (int64_t i = 0; i < n_pts; ++i)
+    dgref::eval_basis(dim, k, pts + i * dim, vals + i * np, grads ? grads + i * np * dim : nullptr);
+  return DG_OK;
+}
+
+dg_status dg_mesh_get_info(const dg_mesh* m, dg_mesh_info* out) {
+  if (!m || !out) return fail(DG_EINVAL, "null pointer");
+  out->dim = m->h.dim;
+  out->k = m->h.k;
+  out->n_basis = m->h.np;
+  out->n_elem = m->h.E;
+  out->n_facet = m->h.E * (m->h.dim + 1) / 2;
+  out->n_dof = m->h.E * m->h.dim * m->h.np;
+  out->nq_vol = m->t.nq;
+  out->nq_facet = m->t.nfq;
+  out->n_types = m->h.ntypes;
+  out->n_tiles = m->h.ntiles;
+  out->h_min = m->h.hmin;
+  out->volume = m->h.volume;
+  return DG_OK;
+}
+
+dg_status dg_mesh_get_vertices(const dg_mesh* m, double* xyz_out) {
+  if (!m || !xyz_out) return fail(DG_EINVAL, "null pointer");
+  std::memcpy(xyz_out, m->h.X.data(), m->h.X.size() * sizeof(double));
+  return DG_OK;
+}
+
+dg_status dg_mesh_get_neighbors(const dg_mesh* m, int32_t* nbr_out, int32_t* nbr_facet_out) {
+  if (!m || !nbr_out || !nbr_facet_out) return fail(DG_EINVAL, "null pointer");
+  std::memcpy(nbr_out, m->h.nbr.data(), m->h.nbr.size() * sizeof(int32_t));
+  std::memcpy(nbr_facet_out, m->h.nbr_facet.data(), m->h.nbr_facet.size() * sizeof(int32_t));
+  return DG_OK;
+}
+
+dg_status dg_project_points(const dg_mesh* m, int n, double* xyz_out) {
+  if (!m || !xyz_out) return fail(DG_EINVAL, "null pointer");
+  if (n < 1 || n > 32) return fail(DG_EINVAL, "n must be in 1..32");
+  const int d = m->h.dim, nv = d + 1;
+  std::vector<double> p, w;
+  dgref::collapsed_rule<double>(d, n, p, w);
+  const size_t nq = w.size();
+  for (int64_t t = 0; t < m->h.E; ++t) {
+    const double* X = &m->h.X[(size_t)t * nv * d];
+    for (size_t q = 0; q < nq; ++q)
+      for (int i = 0; i < d; ++i) {
+        double x = X[i];
+        for (int j = 0; j < d; ++j) x += (X[(j + 1) * d + i] - X[i]) * p[q * d + j];
+        xyz_out[((size_t)t * nq + q) * d + i] = x;
+      }
+  }
+  return DG_OK;
+}
+
+dg_status dg_project(const dg_mesh* m, int n, const double* vals, double* coef_out) {
+  if (!m || !vals || !coef_out) return fail(DG_EINVAL, "null pointer");
+  if (n < 1 || n > 32) return fail(DG_EINVAL, "n must be in 1..32");
+  const int d = m->h.dim, np = m->h.np;
+  std::vector<double> p, w;
+  dgref::collapsed_rule<double>(d, n, p, w);
+  const size_t nq = w.size();
+  std::vector<double> phi(nq * np);
+  for (size_t q = 0; q < nq; ++q) dgref::eval_basis(d, m->h.k, &p[q * d], &phi[q * np], nullptr);
+  // orthonormal reference basis: c_m = int_T^ f phi_m dxi (the |det J| of M_T cancels)
+  for (int64_t t = 0; t < m->h.E; ++t)
+    for (int i = 0; i < d; ++i)
+      for (int mm = 0; mm < np; ++mm) {
+        double s = 0;
+        for (size_t q = 0; q < nq; ++q) s += w[q] * phi[q * np + mm] * vals[((size_t)t * nq + q) * d + i];
+        coef_out[((size_t)t * d + i) * np + mm] = s;
+      }
+  return DG_OK;
+}
+
+dg_status dg_convection_apply(const dg_mesh* m, dg_precision prec, const void* w, const void* u,
+                              void* r, void* stream) {
+  if (!m || !w || !r) return fail(DG_EINVAL, "null pointer");
+  if (!aligned16(w) || !aligned16(r) || (u && !aligned16(u)))
+    return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
+  if (r == w || r == u) return fail(DG_EINVAL, "r must not alias w or u");
+  if (prec != DG_FP64 && prec != DG_FP32)
+    return fail(DG_EUNSUPPORTED, "precision not available for dg_convection_apply");
+  dg_status st = ensure_device(m);
+  if (st != DG_OK) return st;
+  const hipStream_t s = (hipStream_t)stream;
+  switch (prec) {
+    case DG_FP64: return run_apply<double>(m, w, u, r, s);
+    case DG_FP32: return run_apply<float>(m, w, u, r, s);
+    default: return fail(DG_EUNSUPPORTED, "precision not available for dg_convection_apply");
+  }
+}
+
+dg_status dg_rk_substeps(const dg_mesh* m, dg_precision prec, void* w, double dt, int n,
+                         const void* u, void* work, void* stream) {
+  if (!m || !w) return fail(DG_EINVAL, "null pointer");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be positive and finite");
+  if (n < 0) return fail(DG_EINVAL, "n must be >= 0");
+  if (!aligned16(w) || (u && !aligned16(u)) || (work && !aligned16(work)))
+    return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
+  if (u == w) return fail(DG_EINVAL, "u must not alias w");
+  if (prec != DG_FP64 && prec != DG_FP32)
+    return fail(DG_EUNSUPPORTED, "precision not available for dg_rk_substeps");
+  dg_status st = ensure_device(m);
+  if (st != DG_OK) return st;
+  std::lock_guard<std::mutex> lock(const_cast<dg_mesh*>(m)->mu);
+  const size_t esz = prec == DG_FP64 ? 8 : 4;
+  const size_t bytes = 2 * (size_t)m->h.E * m->h.dim * m->h.np * esz + 16;
+  if (!work) {
+    if (m->work_bytes < bytes) {
+      if (m->d_work) HIP_TRY(hipFree(m->d_work));
+      m->d_work = nullptr;
+      m->work_bytes = 0;
+      HIP_TRY(hipMalloc(&m->d_work, bytes));
+      m->work_bytes = bytes;
+    }
+    work = m->d_work;
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  return prec == DG_FP64 ? run_rk<double>(m, w, dt, n, u, work, s)
+                         : run_rk<float>(m, w, dt, n, u, work, s);
+}
+
+dg_status dg_reduce(const dg_mesh* m, int what, const double* a, const double* b,
+                    double* out_dev, void* stream) {
+  if (!m || !a || !out_dev) return fail(DG_EINVAL, "null pointer");
+  if (what == DG_RED_L2DIFF && !b) return fail(DG_EINVAL, "L2DIFF needs b");
+  if (what < DG_RED_MAXVEL || what > DG_RED_NONFINITE) return fail(DG_EINVAL, "unknown reduction");
+  dg_status st = ensure_device(m);
+  if (st != DG_OK) return st;
+  const hipStream_t s = (hipStream_t)stream;
+  const int nb = m->n_partial, d = m->h.dim;
+  if (what == DG_RED_MAXVEL) {
+    hipError_t e = hipErrorInvalidValue;
+    const int k = m->h.k;
+#define DG_CASE(D_, K_) \
+  if (d == D_ && k == K_) e = launch_maxvel<D_, K_>(m, a, s);
+    DG_CASE(2, 0) DG_CASE(2, 1) DG_CASE(2, 2) DG_CASE(2, 3) DG_CASE(2, 4) DG_CASE(2, 5)
+    DG_CASE(2, 6) DG_CASE(3, 0) DG_CASE(3, 1) DG_CASE(3, 2) DG_CASE(3, 3) DG_CASE(3, 4)
+#undef DG_CASE
+    HIP_TRY(e);
+    hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(kRedBlock), 0, s, nb, 1, 1, 0,
+                       m->d_partial, out_dev);
+    HIP_TRY(hipGetLastError());
+    return DG_OK;
+  }
+  if (what < DG_RED_ENERGY || what > DG_RED_NONFINITE) return fail(DG_EINVAL, "unknown reduction");
+  const double phi0_vol = d == 2 ? std::sqrt(2.0) * 0.5 : std::sqrt(6.0) / 6.0;
+  hipLaunchKernelGGL(elem_reduce_kernel, dim3(nb), dim3(kRedBlock), 0, s, what, d, m->h.np,
+                     m->h.E, a, b, m->d_absdet, phi0_vol, m->d_partial);
+  HIP_TRY(hipGetLastError());
+  const int nout = what == DG_RED_MOMENTUM ? d : (what == DG_RED_L2DIFF ? 2 : 1);
+  hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(kRedBlock), 0, s, nb, 0, nout,
+                     what == DG_RED_L2DIFF ? 1 : 0, m->d_partial, out_dev);
+  HIP_TRY(hipGetLastError());
+  return DG_OK;
+}
+
+}  // extern "C"

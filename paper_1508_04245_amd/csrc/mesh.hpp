@@ -1,0 +1,54 @@
+// Host-side mesh processing: element geometry, periodic facet matching, canonical facet
+// orientation, element classes ("types") with identical facet tables, and the reference
+// tables the kernels read.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace dgmesh {
+
+struct Host {
+  int dim = 0, k = 0, np = 0;
+  int64_t E = 0;
+  std::vector<double> X;          // [E][d+1][d] unwrapped vertex coordinates
+  std::vector<double> jinv;       // [E][d][d]  (J^-1)_{row, col}
+  std::vector<double> absdet;     // [E]
+  std::vector<int32_t> nbr;       // [E][d+1]
+  std::vector<int32_t> nbr_facet; // [E][d+1]
+  std::vector<uint8_t> perm_own;  // [E][d+1] canonical-order permutation code, own side
+  std::vector<uint8_t> perm_nbr;  // [E][d+1] same for the neighbour's facet
+  double hmin = 0, volume = 0;
+  // element classes
+  std::vector<int32_t> type_of;   // [E]
+  int ntypes = 0;
+  std::vector<int32_t> type_tab;  // [ntypes][d+1]: (own table) | (nbr table << 16)
+  std::vector<int32_t> elem_list; // [ntiles*64], -1 padded
+  std::vector<int32_t> tile_type; // [ntiles]
+  int ntiles = 0;
+};
+
+// returns empty string on success, else an error message; code set to a dg_status value
+int build(int dim, int k, int64_t nvert, const double* xyz, int64_t nelem, const int64_t* elem,
+          const double* period, Host& out, std::string& err);
+
+void box_connectivity(int dim, int n, std::vector<double>& xyz, std::vector<int64_t>& elem);
+
+// Tables (FP64) for the kernels, concatenated:
+//   Bv [nq][np]            phi_m at the volume points
+//   Dv [nq][np][d]         w_q d phi_m / d xi_j at the volume points
+//   Tr [(d+1)*P][nfq][np]  phi_m at the canonical facet points of local facet f with
+//                          canonical permutation p (table index f*P + p, P = d!)
+//   Lf [(d+1)*P][nfq][np]  facet weight times Tr
+struct Tables {
+  int nq = 0, nfq = 0, nperm = 0;
+  size_t off_bv = 0, off_dv = 0, off_tr = 0, off_lf = 0, total = 0;
+  std::vector<double> data;
+};
+void build_tables(int dim, int k, Tables& t);
+
+int n_perm(int dim);
+// the canonical vertex order of local facet f under permutation code p: local vertex ids
+void canonical_vertices(int dim, int f, int p, int* out);
+
+}  // namespace dgmesh

@@ -1,0 +1,138 @@
+"""Host-side checks of the C ABI (no GPU): symbols, mesh processing, basis, projection, errors.
+
+These compare the library's host code (its own basis recurrences, Gauss rules, facet matching)
+with the oracle, which shares no code with it.
+"""
+import ctypes
+import itertools
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1508_04245_amd as dg
+from oracle import refelem as R
+from oracle.dg import Space
+from oracle.mesh import Mesh as OMesh, box_mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "dgconv.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dg_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    L = dg.lib()
+    names = header_functions()
+    assert "dg_convection_apply" in names and "dg_rk_substeps" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert b"gfx950" in L.dg_version()
+
+
+def lattice_mesh(dim, N, jitter=0.0, seed=0):
+    """(N+1)^dim vertex array + connectivity in the oracle box ordering (+ periodic jitter)."""
+    h = 1.0 / N
+    rng = np.random.default_rng(seed)
+    off = rng.uniform(-1, 1, size=(N,) * dim + (dim,)) * jitter * h if jitter else None
+    grid = np.stack(np.meshgrid(*([np.arange(N + 1)] * dim), indexing="ij"), -1)
+    grid = np.moveaxis(grid, list(range(dim)), list(range(dim))[::-1]).reshape(-1, dim)
+    # vertex id = i + (N+1) j (+ (N+1)^2 l), coordinates lattice * h (+ jitter of the wrap)
+    xyz = grid * h
+    if off is not None:
+        xyz = xyz + off[tuple(np.mod(grid[:, a], N) for a in range(dim))]
+    vid = lambda idx: sum(int(idx[a]) * (N + 1) ** a for a in range(dim))
+    elem = []
+    if dim == 2:
+        for j in range(N):
+            for i in range(N):
+                b = np.array([i, j])
+                elem.append([vid(b), vid(b + [1, 0]), vid(b + [1, 1])])
+                elem.append([vid(b + [1, 1]), vid(b + [0, 1]), vid(b)])
+    else:
+        eye = np.eye(3, dtype=int)
+        for l in range(N):
+            for j in range(N):
+                for i in range(N):
+                    b = np.array([i, j, l])
+                    for s in itertools.permutations(range(3)):
+                        elem.append([vid(b), vid(b + eye[s[0]]), vid(b + eye[s[0]] + eye[s[1]]),
+                                     vid(b + 1)])
+    return xyz, np.array(elem, dtype=np.int64)
+
+
+@pytest.mark.parametrize("dim,N", [(2, 4), (2, 1), (3, 3), (3, 1)])
+def test_box_mesh_matches_oracle(dim, N):
+    m = dg.Mesh.box(dim, N, 2)
+    om = box_mesh(dim, N)
+    assert m.E == om.E
+    assert np.array_equal(m.vertices(), om.X)
+    nb, nf = m.neighbors()
+    assert np.array_equal(nb, om.nbr) and np.array_equal(nf, om.nbr_facet)
+    assert 1 <= m.info["n_types"] <= (2 if dim == 2 else 6)
+    assert np.isclose(m.info["volume"], 1.0)
+
+
+@pytest.mark.parametrize("dim,N,jit", [(2, 5, 0.25), (3, 3, 0.2)])
+def test_general_mesh_matches_oracle(dim, N, jit):
+    xyz, elem = lattice_mesh(dim, N, jit, seed=3)
+    m = dg.Mesh.from_arrays(dim, 2, xyz, elem, np.ones(dim))
+    om = OMesh(xyz[elem], np.ones(dim))
+    nb, nf = m.neighbors()
+    assert np.array_equal(nb, om.nbr) and np.array_equal(nf, om.nbr_facet)
+    assert m.info["n_types"] >= (2 if dim == 2 else 6)
+
+
+@pytest.mark.parametrize("dim,k", [(2, 0), (2, 3), (2, 6), (3, 1), (3, 4)])
+def test_basis_matches_oracle(dim, k):
+    rng = np.random.default_rng(0)
+    pts = rng.dirichlet(np.ones(dim + 1), size=50)[:, :dim]
+    pts = np.vstack([pts, R.ref_vertices(dim)])  # vertices too (collapsed-coordinate poles)
+    v, g = dg.eval_basis(dim, k, pts)
+    assert np.abs(v - R.eval_basis(dim, k, pts)).max() < 1e-12
+    inner = pts[:50]
+    ge = R.eval_grad(dim, k, inner)
+    assert np.abs(g[:50] - ge).max() <= 1e-13 * max(1.0, np.abs(ge).max())
+
+
+@pytest.mark.parametrize("dim,k,n", [(2, 4, 9), (3, 2, 6)])
+def test_projection_matches_oracle(dim, k, n):
+    from paper_1508_04245_amd import synth
+    m = dg.Mesh.box(dim, 3, k)
+    sp = Space(box_mesh(dim, 3), k)
+    x = m.project_points(n)
+    assert np.abs(x - sp.quad_points(n)).max() < 1e-15
+    f = synth.taylor_green_2d(x) if dim == 2 else synth.taylor_green_3d(x)
+    c = m.project(f, n)
+    assert np.abs(c - sp.project(f, n)).max() < 1e-13
+
+
+def test_error_paths():
+    with pytest.raises(dg.DGError) as e:
+        dg.Mesh.box(4, 2, 1)
+    assert e.value.status == -1
+    with pytest.raises(dg.DGError) as e:
+        dg.Mesh.box(3, 2, 5)
+    assert e.value.status == -4
+    # non-periodic use of a box: facets on the boundary are unmatched
+    xyz, elem = lattice_mesh(2, 3)
+    with pytest.raises(dg.DGError) as e:
+        dg.Mesh.from_arrays(2, 1, xyz, elem, np.array([2.0, 2.0]))
+    assert e.value.status == -6
+    # degenerate element
+    xyz2 = xyz.copy()
+    bad = elem.copy()
+    bad[0] = [bad[0][0], bad[0][0], bad[0][2]]
+    with pytest.raises(dg.DGError) as e:
+        dg.Mesh.from_arrays(2, 1, xyz2, bad, np.ones(2))
+    assert e.value.status == -6
+    # vertex id out of range
+    bad = elem.copy()
+    bad[3, 1] = 10 ** 6
+    with pytest.raises(dg.DGError) as e:
+        dg.Mesh.from_arrays(2, 1, xyz, bad, np.ones(2))
+    assert e.value.status == -1
