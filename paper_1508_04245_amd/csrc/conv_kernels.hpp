@@ -1,10 +1,15 @@
 // CDNA4 (gfx950) kernels of the upwind-DG convection operator, plain FP64 / FP32 path.
 //
 // One lane per element, one wavefront per 64-element tile of a single element class
-// (identical facet tables), so every table entry a lane needs is wave-uniform: tables are
-// read through constant-address-space pointers with uniform offsets and arrive in SGPRs
-// (scalar loads), and each multiply-add of a basis contraction is a VALU FMA with one scalar
-// operand.  The per-element state, the neighbour states and the accumulators stay in VGPRs.
+// (identical facet tables), so every table entry a lane needs is wave-uniform.  A workgroup
+// (4 wavefronts) covers one block of 256 consecutive elements, so all writes to a cache line
+// of the state come from one CU, and hardware blocks are remapped so that each XCD (blocks
+// are dealt round-robin over the 8 XCDs) works on one contiguous range of the mesh and finds
+// most neighbour states in its own L2.  Tables are staged in LDS when they fit (64 KiB) and
+// read with wave-uniform addresses (broadcast reads, returned in order so the compiler can
+// pipeline them); larger tables are read through constant-address-space pointers (scalar
+// loads into SGPRs).  Each multiply-add of a basis contraction is one VALU FMA.  The
+// per-element state, the neighbour states and the accumulators stay in VGPRs.
 //
 // Per element and application (Sec. 2.3 upwind form, Sec. 2.4 discrete operator, inverse of
 // the diagonal mass matrix folded in):
@@ -58,19 +63,54 @@ __device__ __forceinline__ T nref(int f, int j) {
   return j == f - 1 ? (D == 2 ? T(-1) : T(-0.5)) : T(0);
 }
 
-template <int D, int K, typename T, bool SELF>
-__global__ void __launch_bounds__(256) conv_kernel(ConvArgs<T> A) {
+// tables fit in LDS (bytes)
+template <int D, int K, typename T>
+constexpr bool tables_in_lds() { return Shape<D, K>::TOTAL * sizeof(T) <= 65536; }
+
+// hardware block -> logical block: XCD x = b % 8 gets the contiguous logical range
+// [x q + min(x, r), ...) of q + (x < r) blocks, q = n / 8, r = n % 8 (a bijection of [0, n))
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  const int x = b & 7, j = b >> 3, q = n >> 3, r = n & 7;
+  return x * q + (x < r ? x : r) + j;
+}
+
+template <bool LDS, typename T>
+struct Tab {
+  typedef const T __attribute__((address_space(4)))* cptr;
+  const T* l;
+  cptr c;
+  __device__ __forceinline__ T operator[](int i) const {
+    if constexpr (LDS) return l[i];
+    else return c[i];
+  }
+};
+
+// occupancy target: two waves per SIMD (<= 256 VGPR+AGPR per lane) where the state fits
+template <int D, int K, typename T>
+constexpr int min_waves() { return Shape<D, K>::NP * D * sizeof(T) <= 15 * 2 * 8 ? 2 : 1; }
+
+template <int D, int K, typename T, bool SELF, bool LDS>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvArgs<T> A) {
   using S = Shape<D, K>;
   constexpr int NP = S::NP;
-  typedef const T __attribute__((address_space(4)))* cptr;
   typedef const int __attribute__((address_space(4)))* ciptr;
   const int lane = threadIdx.x & 63;
-  const int tile = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (tile >= A.ntiles) return;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int tile = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
+  Tab<LDS, T> tab;
+  if constexpr (LDS) {
+    __shared__ T stab[LDS ? S::TOTAL : 1];
+    for (int i = threadIdx.x; i < S::TOTAL; i += 256) stab[i] = A.tab[i];
+    __syncthreads();
+    tab.l = stab;
+  } else {
+    tab.c = (typename Tab<LDS, T>::cptr)A.tab;
+  }
+  const int type = __builtin_amdgcn_readfirstlane(A.tile_type[tile]);
+  if (type < 0) return;  // empty tile padding a block
   const int e_raw = A.elem_list[tile * 64 + lane];
   const int e = e_raw >= 0 ? e_raw : A.elem_list[tile * 64];  // padded lanes redo lane 0
-  const int type = __builtin_amdgcn_readfirstlane(A.tile_type[tile]);
-  const cptr tab = (cptr)A.tab;
   const ciptr ttab = (ciptr)A.type_tab;
 
   T c[D][NP], uc[SELF ? 1 : D][SELF ? 1 : NP], R[D][NP], ji[D][D];
@@ -101,14 +141,14 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs<T> A) {
   // ---- volume term
 #pragma unroll 1
   for (int q = 0; q < S::NQ; ++q) {
-    const cptr bq = tab + S::OFF_BV + q * NP;
-    const cptr dq = tab + S::OFF_DV + q * NP * D;
+    const int bq = S::OFF_BV + q * NP;
+    const int dq = S::OFF_DV + q * NP * D;
     T wq[D], uq[D], uh[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) wq[i] = T(0);
 #pragma unroll
     for (int m = 0; m < NP; ++m) {
-      const T bm = bq[m];
+      const T bm = tab[bq + m];
 #pragma unroll
       for (int i = 0; i < D; ++i) wq[i] = fma(bm, c[i][m], wq[i]);
     }
@@ -120,7 +160,7 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs<T> A) {
       for (int i = 0; i < D; ++i) uq[i] = T(0);
 #pragma unroll
       for (int m = 0; m < NP; ++m) {
-        const T bm = bq[m];
+        const T bm = tab[bq + m];
 #pragma unroll
         for (int i = 0; i < D; ++i) uq[i] = fma(bm, uc[i][m], uq[i]);
       }
@@ -136,7 +176,7 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs<T> A) {
     for (int m = 0; m < NP; ++m) {
       T P = T(0);
 #pragma unroll
-      for (int a = 0; a < D; ++a) P = fma(uh[a], dq[m * D + a], P);
+      for (int a = 0; a < D; ++a) P = fma(uh[a], tab[dq + m * D + a], P);
 #pragma unroll
       for (int i = 0; i < D; ++i) R[i][m] = fma(wq[i], P, R[i][m]);
     }
@@ -148,9 +188,9 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs<T> A) {
     const int tt = ttab[type * (D + 1) + f];
     const int own = __builtin_amdgcn_readfirstlane(tt & 0xffff);
     const int nbt = __builtin_amdgcn_readfirstlane(tt >> 16);
-    const cptr tro = tab + S::OFF_TR + own * S::NFQ * NP;
-    const cptr trn = tab + S::OFF_TR + nbt * S::NFQ * NP;
-    const cptr lfo = tab + S::OFF_LF + own * S::NFQ * NP;
+    const int tro = S::OFF_TR + own * S::NFQ * NP;
+    const int trn = S::OFF_TR + nbt * S::NFQ * NP;
+    const int lfo = S::OFF_LF + own * S::NFQ * NP;
     const int ne = A.nbr[(size_t)e * (D + 1) + f];
     T cn[D][NP], un[SELF ? 1 : D][SELF ? 1 : NP];
     {
@@ -182,7 +222,7 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs<T> A) {
       for (int i = 0; i < D; ++i) { wm[i] = T(0); wp[i] = T(0); }
 #pragma unroll
       for (int m = 0; m < NP; ++m) {
-        const T to = tro[q * NP + m], tn = trn[q * NP + m];
+        const T to = tab[tro + q * NP + m], tn = tab[trn + q * NP + m];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
           wm[i] = fma(to, c[i][m], wm[i]);
@@ -197,7 +237,7 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs<T> A) {
         for (int i = 0; i < D; ++i) { um[i] = T(0); up[i] = T(0); }
 #pragma unroll
         for (int m = 0; m < NP; ++m) {
-          const T to = tro[q * NP + m], tn = trn[q * NP + m];
+          const T to = tab[tro + q * NP + m], tn = tab[trn + q * NP + m];
 #pragma unroll
           for (int i = 0; i < D; ++i) {
             um[i] = fma(to, uc[i][m], um[i]);
@@ -216,7 +256,7 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs<T> A) {
       for (int i = 0; i < D; ++i) F[i] = hb * (wm[i] + wp[i]) + ha * (wm[i] - wp[i]);
 #pragma unroll
       for (int m = 0; m < NP; ++m) {
-        const T l = lfo[q * NP + m];
+        const T l = tab[lfo + q * NP + m];
 #pragma unroll
         for (int i = 0; i < D; ++i) R[i][m] = fma(-l, F[i], R[i][m]);
       }
@@ -224,7 +264,7 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs<T> A) {
   }
 
   if (e_raw < 0) return;
-  T* __restrict__ o = A.out + (size_t)e * D * NP;
+  T* o = A.out + (size_t)e * D * NP;
   if (A.mode == 0) {
 #pragma unroll
     for (int i = 0; i < D; ++i)
@@ -233,12 +273,20 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvArgs<T> A) {
   } else {
     const T a = A.a, b = A.b, dt = A.dt;
     if (a != T(0)) {
-      const T* __restrict__ pw = A.w0 + (size_t)e * D * NP;
+      // all loads of w0 before any store: out may be w0 itself (in-place last stage), and
+      // back-to-back stores let whole cache lines complete in L2 before eviction
+      const T* pw = A.w0 + (size_t)e * D * NP;
+      T w0v[D][NP];
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int m = 0; m < NP; ++m) w0v[i][m] = pw[i * NP + m];
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int i = 0; i < D; ++i)
 #pragma unroll
         for (int m = 0; m < NP; ++m)
-          o[i * NP + m] = fma(a, pw[i * NP + m], b * fma(dt, R[i][m], c[i][m]));
+          o[i * NP + m] = fma(a, w0v[i][m], b * fma(dt, R[i][m], c[i][m]));
     } else {
 #pragma unroll
       for (int i = 0; i < D; ++i)

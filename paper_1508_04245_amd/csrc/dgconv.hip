@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -56,6 +57,7 @@ struct dg_mesh {
   double* d_partial = nullptr;  // reduction partials
   int n_partial = 0;
   bool on_device = false;
+  bool tables_lds = false;  // stage reference tables in LDS (where they fit) or read via SGPRs
   std::mutex mu;
 };
 
@@ -173,12 +175,16 @@ hipError_t launch_maxvel(const dg_mesh* m, const double* a, hipStream_t s) {
 
 template <int D, int K, typename T, bool SELF>
 hipError_t launch_conv_dk(const dg_mesh* m, const dgk::ConvArgs<T>& a, hipStream_t s) {
+  constexpr bool kLdsOk = dgk::tables_in_lds<D, K, T>();
   // the kernel's compile-time table layout must match the host tables it reads
   if ((size_t)dgk::Shape<D, K>::TOTAL != m->t.total || dgk::Shape<D, K>::NP != m->h.np)
     return hipErrorInvalidValue;
   if ((int64_t)m->h.elem_list.size() != (int64_t)m->h.ntiles * 64) return hipErrorInvalidValue;
   const dim3 grid((m->h.ntiles + 3) / 4), block(256);
-  hipLaunchKernelGGL((dgk::conv_kernel<D, K, T, SELF>), grid, block, 0, s, a);
+  if (kLdsOk && m->tables_lds)
+    hipLaunchKernelGGL((dgk::conv_kernel<D, K, T, SELF, kLdsOk>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((dgk::conv_kernel<D, K, T, SELF, false>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
@@ -327,6 +333,12 @@ dg_status dg_mesh_create(int dim, int k, int64_t n_vert, const double* xyz, int6
   }
   dgmesh::build_tables(dim, k, m->t);
   m->n_partial = (int)((n_elem + kRedBlock - 1) / kRedBlock);
+  {
+    // LDS tables by default (measured faster on c2: 57 us vs 88 us per launch);
+    // DGCONV_TABLES=smem reads them through scalar loads instead
+    const char* tm = std::getenv("DGCONV_TABLES");
+    m->tables_lds = !(tm && std::string(tm) == "smem");
+  }
   *out = m;
   return DG_OK;
 }

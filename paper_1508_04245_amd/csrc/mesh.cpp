@@ -244,15 +244,30 @@ int build(int dim, int k, int64_t nvert, const double* xyz, int64_t nelem, const
       H.type_tab[ty * nf + f] = own | (nb << 16);
     }
   }
-  std::vector<std::vector<int32_t>> members(H.ntypes);
-  for (int64_t t = 0; t < nelem; ++t) members[H.type_of[t]].push_back((int32_t)t);
+  // Tiles: the mesh is cut into blocks of 256 consecutive elements (one workgroup each);
+  // inside a block the elements are grouped by class into 64-wide tiles, and the block's
+  // tile count is padded to a multiple of 4 with empty tiles, so that every tile of a
+  // workgroup covers the same contiguous range of the state arrays.
   H.elem_list.clear();
   H.tile_type.clear();
-  for (int ty = 0; ty < H.ntypes; ++ty) {
-    const auto& mm = members[ty];
-    for (size_t s = 0; s < mm.size(); s += 64) {
-      for (size_t l = 0; l < 64; ++l) H.elem_list.push_back(s + l < mm.size() ? mm[s + l] : -1);
-      H.tile_type.push_back(ty);
+  for (int64_t b0 = 0; b0 < nelem; b0 += 256) {
+    const int64_t b1 = std::min<int64_t>(nelem, b0 + 256);
+    std::map<int, std::vector<int32_t>> by_type;
+    for (int64_t t = b0; t < b1; ++t) by_type[H.type_of[t]].push_back((int32_t)t);
+    int ntile_block = 0;
+    for (auto& kv : by_type) {
+      const auto& mm = kv.second;
+      for (size_t s0 = 0; s0 < mm.size(); s0 += 64) {
+        for (size_t l = 0; l < 64; ++l)
+          H.elem_list.push_back(s0 + l < mm.size() ? mm[s0 + l] : -1);
+        H.tile_type.push_back(kv.first);
+        ++ntile_block;
+      }
+    }
+    while (ntile_block % 4) {
+      for (int l = 0; l < 64; ++l) H.elem_list.push_back(-1);
+      H.tile_type.push_back(-1);
+      ++ntile_block;
     }
   }
   H.ntiles = (int)H.tile_type.size();
