@@ -112,7 +112,10 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "f16x2", "bf16x3"])
+    ap.add_argument("--fp64-kernel", default=None, choices=["valu", "mfma"],
+                    help="FP64 operator kernel (default: the library's choice)")
+    ap.add_argument("--n", type=int, default=None, help="override the mesh size (experiments)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     args = ap.parse_args()
@@ -121,14 +124,18 @@ def main():
               " not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.fp64_kernel:
+        os.environ["DGCONV_FP64_KERNEL"] = args.fp64_kernel
     import torch
     import paper_1508_04245_amd as dg
     dg.lib()
-    cfg = CONFIGS[args.config]
+    cfg = dict(CONFIGS[args.config])
+    if args.n:
+        cfg["n"] = args.n
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     m, w_host = make_state(dg, cfg)
-    ty = torch.float64 if args.precision == "fp64" else torch.float32
+    ty = torch.float32 if args.precision == "fp32" else torch.float64
     w = torch.tensor(w_host, dtype=ty, device=dev)
     w64 = torch.tensor(w_host, dtype=torch.float64, device=dev)
     umax = float(m.reduce("maxvel", w64)[0].item())
@@ -136,12 +143,13 @@ def main():
     dt = 0.1 * h / (max(cfg["k"], 1) ** 2 * umax)
     stream = torch.cuda.current_stream()
     work = torch.empty((2,) + tuple(w.shape), dtype=ty, device=dev)
-    m.rk_substeps(w, dt, args.warmup, work=work)
+    prec = args.precision
+    m.rk_substeps(w, dt, args.warmup, work=work, precision=prec)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(stream)
-    m.rk_substeps(w, dt, args.steps, work=work)
+    m.rk_substeps(w, dt, args.steps, work=work, precision=prec)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0

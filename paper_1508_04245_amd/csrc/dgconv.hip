@@ -12,6 +12,7 @@
 
 #include "../../include/dgconv.h"
 #include "conv_kernels.hpp"
+#include "mfma_kernels.hpp"
 #include "mesh.hpp"
 #include "refelem.hpp"
 
@@ -58,6 +59,11 @@ struct dg_mesh {
   int n_partial = 0;
   bool on_device = false;
   bool tables_lds = false;  // stage reference tables in LDS (where they fit) or read via SGPRs
+  bool fp64_mfma = false;   // FP64 operator on the matrix cores instead of the VALU kernel
+  // matrix-core path: 16-wide tiles and fragment tables per contraction engine
+  int* d_elem_list16 = nullptr;
+  int* d_tile_type16 = nullptr;
+  void* d_frag[3] = {nullptr, nullptr, nullptr};  // 0: f64, 1: fp16 x2, 2: bf16 x3
   std::mutex mu;
 };
 
@@ -255,6 +261,194 @@ dg_status run_rk(const dg_mesh* m, void* w, double dt, int n, const void* u, voi
   return DG_OK;
 }
 
+
+// ------------------------------------------------------------------ matrix-core tables
+// A-operand fragment blocks (see mfma_kernels.hpp) built from the FP64 reference tables.
+// Engine 0: f64 blocks, 256 doubles: [j][lane] = A[lane % 16][4 j + lane / 16].
+// Engines 1, 2: NS pieces of 16-bit values: [piece][lane][j] = piece(A[lane % 16][4 (lane/16) + j]).
+uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+float bf16_value(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+uint16_t f16_bits(double v, double* back) {
+  const _Float16 h = (_Float16)(float)v;
+  *back = (double)(float)h;
+  uint16_t b;
+  std::memcpy(&b, &h, 2);
+  return b;
+}
+
+std::vector<uint8_t> build_frags(const dgmesh::Tables& t, int d, int np, int engine) {
+  const int nq = t.nq, nfq = t.nfq, ntab = (d + 1) * t.nperm;
+  const int KP = (np + 15) / 16, QT = (nq + 15) / 16, FT = (nfq + 15) / 16;
+  const int nblk = QT * KP + d * KP * QT + ntab * FT * KP + ntab * KP * FT;
+  const int ns = engine == 0 ? 1 : (engine == 1 ? 2 : 3);
+  const size_t blk_bytes = engine == 0 ? 256 * 8 : (size_t)ns * 64 * 4 * 2;
+  std::vector<uint8_t> out((size_t)nblk * blk_bytes, 0);
+  auto put = [&](int blk, auto&& A /* (row, col) -> double, 16 x 16 block */) {
+    uint8_t* base = out.data() + (size_t)blk * blk_bytes;
+    for (int lane = 0; lane < 64; ++lane)
+      for (int j = 0; j < 4; ++j) {
+        if (engine == 0) {
+          ((double*)base)[j * 64 + lane] = A(lane % 16, 4 * j + lane / 16);
+          continue;
+        }
+        double rem = A(lane % 16, 4 * (lane / 16) + j);
+        for (int p = 0; p < ns; ++p) {
+          uint16_t bits;
+          double back;
+          if (engine == 1) {
+            bits = f16_bits(rem, &back);
+          } else {
+            bits = bf16_bits((float)rem);
+            back = (double)bf16_value(bits);
+          }
+          rem -= back;
+          ((uint16_t*)base)[((size_t)p * 64 + lane) * 4 + j] = bits;
+        }
+      }
+  };
+  const double* Bv = &t.data[t.off_bv];
+  const double* Dv = &t.data[t.off_dv];
+  const double* Tr = &t.data[t.off_tr];
+  const double* Lf = &t.data[t.off_lf];
+  int blk = 0;
+  for (int qt = 0; qt < QT; ++qt)
+    for (int kc = 0; kc < KP; ++kc, ++blk)
+      put(blk, [&](int r, int c) {
+        const int q = 16 * qt + r, m = 16 * kc + c;
+        return (q < nq && m < np) ? Bv[q * np + m] : 0.0;
+      });
+  for (int j = 0; j < d; ++j)
+    for (int mt = 0; mt < KP; ++mt)
+      for (int qt = 0; qt < QT; ++qt, ++blk)
+        put(blk, [&](int r, int c) {
+          const int m = 16 * mt + r, q = 16 * qt + c;
+          return (q < nq && m < np) ? Dv[(q * np + m) * d + j] : 0.0;
+        });
+  for (int tb = 0; tb < ntab; ++tb)
+    for (int ft = 0; ft < FT; ++ft)
+      for (int kc = 0; kc < KP; ++kc, ++blk)
+        put(blk, [&](int r, int c) {
+          const int q = 16 * ft + r, m = 16 * kc + c;
+          return (q < nfq && m < np) ? Tr[((size_t)tb * nfq + q) * np + m] : 0.0;
+        });
+  for (int tb = 0; tb < ntab; ++tb)
+    for (int mt = 0; mt < KP; ++mt)
+      for (int ft = 0; ft < FT; ++ft, ++blk)
+        put(blk, [&](int r, int c) {
+          const int m = 16 * mt + r, q = 16 * ft + c;
+          return (q < nfq && m < np) ? -Lf[((size_t)tb * nfq + q) * np + m] : 0.0;
+        });
+  return out;
+}
+
+dg_status ensure_frags(const dg_mesh* cm, int engine) {
+  dg_mesh* m = const_cast<dg_mesh*>(cm);
+  std::lock_guard<std::mutex> lock(m->mu);
+  if (m->d_frag[engine]) return DG_OK;
+  const auto bytes = build_frags(m->t, m->h.dim, m->h.np, engine);
+  HIP_TRY(hipMalloc(&m->d_frag[engine], bytes.size()));
+  HIP_TRY(hipMemcpy(m->d_frag[engine], bytes.data(), bytes.size(), hipMemcpyHostToDevice));
+  return DG_OK;
+}
+
+template <int D, int K, class E, bool SELF>
+hipError_t launch_mconv_dk(const dg_mesh* m, const dgm::MArgs<double>& a, hipStream_t s) {
+  if ((size_t)m->h.elem_list16.size() != (size_t)m->h.ntiles16 * 16 || m->h.ntiles16 % 4)
+    return hipErrorInvalidValue;
+  const dim3 grid(m->h.ntiles16 / 4), block(256);
+  hipLaunchKernelGGL((dgm::mconv_kernel<D, K, E, SELF>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+template <class E, bool SELF>
+hipError_t launch_mconv(const dg_mesh* m, const dgm::MArgs<double>& a, hipStream_t s) {
+  const int d = m->h.dim, k = m->h.k;
+#define DG_CASE(D_, K_) \
+  if (d == D_ && k == K_) return launch_mconv_dk<D_, K_, E, SELF>(m, a, s);
+  DG_CASE(2, 0) DG_CASE(2, 1) DG_CASE(2, 2) DG_CASE(2, 3) DG_CASE(2, 4) DG_CASE(2, 5)
+  DG_CASE(2, 6) DG_CASE(3, 0) DG_CASE(3, 1) DG_CASE(3, 2) DG_CASE(3, 3) DG_CASE(3, 4)
+#undef DG_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_mconv_any(const dg_mesh* m, int engine, const dgm::MArgs<double>& a,
+                            hipStream_t s) {
+  const bool self = a.u == nullptr;
+  switch (engine) {
+    case 0: return self ? launch_mconv<dgm::EngF64, true>(m, a, s) : launch_mconv<dgm::EngF64, false>(m, a, s);
+    case 1: return self ? launch_mconv<dgm::EngSplit<true, 2>, true>(m, a, s)
+                        : launch_mconv<dgm::EngSplit<true, 2>, false>(m, a, s);
+    default: return self ? launch_mconv<dgm::EngSplit<false, 3>, true>(m, a, s)
+                         : launch_mconv<dgm::EngSplit<false, 3>, false>(m, a, s);
+  }
+}
+
+dgm::MArgs<double> mbase_args(const dg_mesh* m, int engine) {
+  dgm::MArgs<double> a{};
+  a.frag = m->d_frag[engine];
+  a.jinv = m->d_jinv;
+  a.nbr = m->d_nbr;
+  a.elem_list = m->d_elem_list16;
+  a.tile_type = m->d_tile_type16;
+  a.type_tab = m->d_type_tab;
+  a.ntiles = m->h.ntiles16;
+  return a;
+}
+
+// engine of a precision on the matrix-core path, or -1 for the VALU kernels
+int engine_of(const dg_mesh* m, dg_precision prec) {
+  if (prec == DG_MIX_F16x2) return 1;
+  if (prec == DG_MIX_BF16x3) return 2;
+  if (prec == DG_FP64 && m->fp64_mfma) return 0;
+  return -1;
+}
+
+dg_status run_apply_m(const dg_mesh* m, int engine, const void* w, const void* u, void* r,
+                      hipStream_t s) {
+  dg_status st = ensure_frags(m, engine);
+  if (st != DG_OK) return st;
+  auto a = mbase_args(m, engine);
+  a.x = (const double*)w;
+  a.u = (const double*)u;
+  a.out = (double*)r;
+  a.mode = 0;
+  HIP_TRY(launch_mconv_any(m, engine, a, s));
+  return DG_OK;
+}
+
+dg_status run_rk_m(const dg_mesh* m, int engine, void* w, double dt, int n, const void* u,
+                   void* work, hipStream_t s) {
+  dg_status st = ensure_frags(m, engine);
+  if (st != DG_OK) return st;
+  const size_t n_state = (size_t)m->h.E * m->h.dim * m->h.np;
+  double* w0 = (double*)w;
+  double* w1 = (double*)work;
+  double* w2 = w1 + n_state;
+  auto a = mbase_args(m, engine);
+  a.u = (const double*)u;
+  a.mode = 1;
+  a.dt = dt;
+  for (int it = 0; it < n; ++it) {
+    a.x = w0; a.w0 = nullptr; a.out = w1; a.a = 0.0; a.b = 1.0;
+    HIP_TRY(launch_mconv_any(m, engine, a, s));
+    a.x = w1; a.w0 = w0; a.out = w2; a.a = 0.75; a.b = 0.25;
+    HIP_TRY(launch_mconv_any(m, engine, a, s));
+    a.x = w2; a.w0 = w0; a.out = w0; a.a = 1.0 / 3.0; a.b = 2.0 / 3.0;
+    HIP_TRY(launch_mconv_any(m, engine, a, s));
+  }
+  return DG_OK;
+}
+
 dg_status check_k(int dim, int k) {
   if (dim != 2 && dim != 3) return fail(DG_EINVAL, "dim must be 2 or 3");
   if (k < 0) return fail(DG_EINVAL, "k must be >= 0");
@@ -293,6 +487,8 @@ dg_status ensure_device(const dg_mesh* cm) {
       (s = upload(m->h.elem_list, &m->d_elem_list)) != DG_OK ||
       (s = upload(m->h.tile_type, &m->d_tile_type)) != DG_OK ||
       (s = upload(m->h.type_tab, &m->d_type_tab)) != DG_OK ||
+      (s = upload(m->h.elem_list16, &m->d_elem_list16)) != DG_OK ||
+      (s = upload(m->h.tile_type16, &m->d_tile_type16)) != DG_OK ||
       (s = upload(zeros, &m->d_partial)) != DG_OK)
     return s;
   m->on_device = true;
@@ -302,7 +498,8 @@ dg_status ensure_device(const dg_mesh* cm) {
 void free_mesh(dg_mesh* m) {
   if (!m) return;
   void* ptrs[] = {m->d_tab, m->d_tab_f, m->d_jinv, m->d_jinv_f, m->d_absdet, m->d_nbr,
-                  m->d_elem_list, m->d_tile_type, m->d_type_tab, m->d_work, m->d_partial};
+                  m->d_elem_list, m->d_tile_type, m->d_type_tab, m->d_work, m->d_partial,
+                  m->d_elem_list16, m->d_tile_type16, m->d_frag[0], m->d_frag[1], m->d_frag[2]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -338,6 +535,11 @@ dg_status dg_mesh_create(int dim, int k, int64_t n_vert, const double* xyz, int6
     // DGCONV_TABLES=smem reads them through scalar loads instead
     const char* tm = std::getenv("DGCONV_TABLES");
     m->tables_lds = !(tm && std::string(tm) == "smem");
+    // FP64 kernel: matrix cores for large elements (n_basis >= 20: measured 2x faster on 3D
+    // P3), the VALU kernel otherwise (faster on 3D P2, equal on 2D P4);
+    // DGCONV_FP64_KERNEL=valu|mfma overrides
+    const char* fk = std::getenv("DGCONV_FP64_KERNEL");
+    m->fp64_mfma = fk ? std::string(fk) == "mfma" : m->h.np >= 20;
   }
   *out = m;
   return DG_OK;
@@ -446,11 +648,13 @@ dg_status dg_convection_apply(const dg_mesh* m, dg_precision prec, const void* w
   if (!aligned16(w) || !aligned16(r) || (u && !aligned16(u)))
     return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
   if (r == w || r == u) return fail(DG_EINVAL, "r must not alias w or u");
-  if (prec != DG_FP64 && prec != DG_FP32)
-    return fail(DG_EUNSUPPORTED, "precision not available for dg_convection_apply");
+  if (prec != DG_FP64 && prec != DG_FP32 && prec != DG_MIX_F16x2 && prec != DG_MIX_BF16x3)
+    return fail(DG_EINVAL, "unknown precision");
   dg_status st = ensure_device(m);
   if (st != DG_OK) return st;
   const hipStream_t s = (hipStream_t)stream;
+  const int engine = engine_of(m, prec);
+  if (engine >= 0) return run_apply_m(m, engine, w, u, r, s);
   switch (prec) {
     case DG_FP64: return run_apply<double>(m, w, u, r, s);
     case DG_FP32: return run_apply<float>(m, w, u, r, s);
@@ -466,14 +670,17 @@ dg_status dg_rk_substeps(const dg_mesh* m, dg_precision prec, void* w, double dt
   if (!aligned16(w) || (u && !aligned16(u)) || (work && !aligned16(work)))
     return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
   if (u == w) return fail(DG_EINVAL, "u must not alias w");
-  if (prec != DG_FP64 && prec != DG_FP32)
-    return fail(DG_EUNSUPPORTED, "precision not available for dg_rk_substeps");
+  if (prec != DG_FP64 && prec != DG_FP32 && prec != DG_MIX_F16x2 && prec != DG_MIX_BF16x3)
+    return fail(DG_EINVAL, "unknown precision");
   dg_status st = ensure_device(m);
   if (st != DG_OK) return st;
-  std::lock_guard<std::mutex> lock(const_cast<dg_mesh*>(m)->mu);
-  const size_t esz = prec == DG_FP64 ? 8 : 4;
-  const size_t bytes = 2 * (size_t)m->h.E * m->h.dim * m->h.np * esz + 16;
+  const int engine = engine_of(m, prec);
+  if (engine >= 0 && (st = ensure_frags(m, engine)) != DG_OK) return st;
   if (!work) {
+    // the mesh-owned work buffer (2 states), grown on demand
+    std::lock_guard<std::mutex> lock(const_cast<dg_mesh*>(m)->mu);
+    const size_t esz = prec == DG_FP32 ? 4 : 8;
+    const size_t bytes = 2 * (size_t)m->h.E * m->h.dim * m->h.np * esz + 16;
     if (m->work_bytes < bytes) {
       if (m->d_work) HIP_TRY(hipFree(m->d_work));
       m->d_work = nullptr;
@@ -484,6 +691,7 @@ dg_status dg_rk_substeps(const dg_mesh* m, dg_precision prec, void* w, double dt
     work = m->d_work;
   }
   const hipStream_t s = (hipStream_t)stream;
+  if (engine >= 0) return run_rk_m(m, engine, w, dt, n, u, work, s);
   return prec == DG_FP64 ? run_rk<double>(m, w, dt, n, u, work, s)
                          : run_rk<float>(m, w, dt, n, u, work, s);
 }

@@ -244,34 +244,41 @@ int build(int dim, int k, int64_t nvert, const double* xyz, int64_t nelem, const
       H.type_tab[ty * nf + f] = own | (nb << 16);
     }
   }
-  // Tiles: the mesh is cut into blocks of 256 consecutive elements (one workgroup each);
-  // inside a block the elements are grouped by class into 64-wide tiles, and the block's
-  // tile count is padded to a multiple of 4 with empty tiles, so that every tile of a
-  // workgroup covers the same contiguous range of the state arrays.
-  H.elem_list.clear();
-  H.tile_type.clear();
-  for (int64_t b0 = 0; b0 < nelem; b0 += 256) {
-    const int64_t b1 = std::min<int64_t>(nelem, b0 + 256);
+  build_tiles(H, 64, H.elem_list, H.tile_type, H.ntiles);
+  build_tiles(H, 16, H.elem_list16, H.tile_type16, H.ntiles16);
+  return 0;
+}
+
+// Tiles of `width` elements: the mesh is cut into blocks of 4*width consecutive elements (one
+// workgroup of 4 wavefronts each); inside a block the elements are grouped by class into
+// tiles, and the block's tile count is padded to a multiple of 4 with empty tiles (class -1),
+// so every tile of a workgroup covers the same contiguous range of the state arrays.
+void build_tiles(const Host& H, int width, std::vector<int32_t>& elem_list,
+                 std::vector<int32_t>& tile_type, int& ntiles) {
+  elem_list.clear();
+  tile_type.clear();
+  const int64_t bsz = 4 * width;
+  for (int64_t b0 = 0; b0 < H.E; b0 += bsz) {
+    const int64_t b1 = std::min<int64_t>(H.E, b0 + bsz);
     std::map<int, std::vector<int32_t>> by_type;
     for (int64_t t = b0; t < b1; ++t) by_type[H.type_of[t]].push_back((int32_t)t);
     int ntile_block = 0;
     for (auto& kv : by_type) {
       const auto& mm = kv.second;
-      for (size_t s0 = 0; s0 < mm.size(); s0 += 64) {
-        for (size_t l = 0; l < 64; ++l)
-          H.elem_list.push_back(s0 + l < mm.size() ? mm[s0 + l] : -1);
-        H.tile_type.push_back(kv.first);
+      for (size_t s0 = 0; s0 < mm.size(); s0 += width) {
+        for (size_t l = 0; l < (size_t)width; ++l)
+          elem_list.push_back(s0 + l < mm.size() ? mm[s0 + l] : -1);
+        tile_type.push_back(kv.first);
         ++ntile_block;
       }
     }
     while (ntile_block % 4) {
-      for (int l = 0; l < 64; ++l) H.elem_list.push_back(-1);
-      H.tile_type.push_back(-1);
+      for (int l = 0; l < width; ++l) elem_list.push_back(-1);
+      tile_type.push_back(-1);
       ++ntile_block;
     }
   }
-  H.ntiles = (int)H.tile_type.size();
-  return 0;
+  ntiles = (int)tile_type.size();
 }
 
 void box_connectivity(int dim, int n, std::vector<double>& xyz, std::vector<int64_t>& elem) {

@@ -23,10 +23,16 @@ struct Host {
   std::vector<int32_t> type_of;   // [E]
   int ntypes = 0;
   std::vector<int32_t> type_tab;  // [ntypes][d+1]: (own table) | (nbr table << 16)
-  std::vector<int32_t> elem_list; // [ntiles*64], -1 padded
-  std::vector<int32_t> tile_type; // [ntiles]
+  std::vector<int32_t> elem_list; // [ntiles*64], -1 padded (64-wide tiles, VALU kernels)
+  std::vector<int32_t> tile_type; // [ntiles], -1 = empty tile
   int ntiles = 0;
+  std::vector<int32_t> elem_list16; // [ntiles16*16] (16-wide tiles, matrix-core kernels)
+  std::vector<int32_t> tile_type16;
+  int ntiles16 = 0;
 };
+
+void build_tiles(const Host& H, int width, std::vector<int32_t>& elem_list,
+                 std::vector<int32_t>& tile_type, int& ntiles);
 
 // returns empty string on success, else an error message; code set to a dg_status value
 int build(int dim, int k, int64_t nvert, const double* xyz, int64_t nelem, const int64_t* elem,

@@ -1,0 +1,128 @@
+"""GPU parity of the matrix-core operator paths against the FP64 oracle.
+
+* FP64 on the matrix cores (v_mfma_f64_16x16x4): the same 1e-12 relative L2 bar as the VALU
+  path.
+* Mixed precision (FP64 state, flux, facet sums and RK; basis contractions as split FP16x2 or
+  BF16x3 products with FP32 accumulation): the error against the FP64 oracle is measured and
+  held below a bound derived from the pieces' precision: two FP16 pieces carry 22 significant
+  bits and three BF16 pieces 24, so each contraction entry carries a relative error of about
+  2^-22 (2.4e-7) or 2^-24 (6e-8) plus FP32 accumulation over 16 terms; the operator amplifies
+  relative errors of its volume and facet terms by their cancellation (~1/(2 pi h)).  The
+  bounds below are 16x the resulting estimate.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_common import C1, C5, initial_state, oracle_space, rel_l2, say
+from oracle.dg import cfl_dt
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import paper_1508_04245_amd as dg
+    assert torch.cuda.is_available()
+    dg.lib()
+    return dg
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def mesh_with(dg, env, factory):
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return factory()
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def lib_mesh(dg, sp, dim, N, k, jit, env):
+    if jit == 0.0:
+        return mesh_with(dg, env, lambda: dg.Mesh.box(dim, N, k))
+    X = sp.mesh.X
+    E = X.shape[0]
+    return mesh_with(dg, env, lambda: dg.Mesh.from_arrays(
+        dim, k, X.reshape(-1, dim), np.arange(E * (dim + 1)).reshape(E, dim + 1), np.ones(dim)))
+
+
+CASES = [(2, k, 5, 0.2) for k in range(7)] + [(3, k, 3, 0.15) for k in range(5)]
+MFMA64 = {"DGCONV_FP64_KERNEL": "mfma"}
+
+
+@pytest.mark.parametrize("dim,k,N,jit", CASES)
+def test_fp64_mfma_apply_all_degrees(dg, dim, k, N, jit):
+    say("case fp64-mfma apply dim=%d k=%d" % (dim, k))
+    sp = oracle_space(dim, N, k, jit, seed=k)
+    m = lib_mesh(dg, sp, dim, N, k, jit, MFMA64)
+    w = initial_state(sp, seed=1, sd=0.05)
+    u = initial_state(sp, field="fourier", seed=2)
+    for uu in (None, u):
+        got = m.apply(dev(w), None if uu is None else dev(uu)).cpu().numpy()
+        ref = sp.apply(w, uu)
+        e = rel_l2(sp, got, ref)
+        say("   rel_l2 %.3e" % e)
+        assert e <= 1e-12
+
+
+def test_fp64_mfma_c1_substeps(dg):
+    dim, N, k = C1
+    say("case fp64-mfma c1 100 substeps")
+    sp = oracle_space(dim, N, k)
+    m = mesh_with(dg, MFMA64, lambda: dg.Mesh.box(dim, N, k))
+    w = initial_state(sp, seed=0)
+    dt = cfl_dt(1.0 / N, k, sp.max_speed(w))
+    wd = dev(w)
+    m.rk_substeps(wd, dt, 100)
+    e = rel_l2(sp, wd.cpu().numpy(), sp.ssprk3(w, dt, 100))
+    say("   rel_l2 %.3e" % e)
+    assert e <= 1e-12
+
+
+BOUND = {"f16x2": 2.0 ** -22, "bf16x3": 2.0 ** -24}
+
+
+@pytest.mark.parametrize("prec", ["f16x2", "bf16x3"])
+@pytest.mark.parametrize("dim,k,N,jit", [(2, 2, 5, 0.2), (2, 4, 4, 0.0), (3, 2, 3, 0.15),
+                                         (3, 3, 2, 0.0)])
+def test_mixed_apply_error(dg, prec, dim, k, N, jit):
+    say("case mixed %s apply dim=%d k=%d" % (prec, dim, k))
+    sp = oracle_space(dim, N, k, jit, seed=k)
+    m = lib_mesh(dg, sp, dim, N, k, jit, {})
+    w = initial_state(sp, seed=1, sd=0.05)
+    got = m.apply(dev(w), precision=prec).cpu().numpy()
+    ref = sp.apply(w)
+    e = rel_l2(sp, got, ref)
+    amp = 1.0 / (2 * np.pi * (1.0 / N))
+    bound = 16 * BOUND[prec] * amp * 4
+    say("   rel_l2 %.3e (bound %.1e)" % (e, bound))
+    assert e <= bound
+
+
+@pytest.mark.parametrize("prec", ["f16x2", "bf16x3"])
+def test_mixed_c5_substeps(dg, prec):
+    dim, N, k = C5
+    say("case mixed %s c5 apply + 4 substeps" % prec)
+    sp = oracle_space(dim, N, k)
+    m = dg.Mesh.box(dim, N, k)
+    w = initial_state(sp, field="fourier", seed=3)
+    r = m.apply(dev(w), precision=prec).cpu().numpy()
+    e_apply = rel_l2(sp, r, sp.apply(w))
+    dt = cfl_dt(1.0 / N, k, sp.max_speed(w))
+    wd = dev(w)
+    m.rk_substeps(wd, dt, 4, precision=prec)
+    e_state = rel_l2(sp, wd.cpu().numpy(), sp.ssprk3(w, dt, 4))
+    say("   apply rel_l2 %.3e  state after 4 substeps rel_l2 %.3e" % (e_apply, e_state))
+    amp = 1.0 / (2 * np.pi / N)
+    assert e_apply <= 64 * BOUND[prec] * amp
+    assert e_state <= 1e-6
