@@ -12,9 +12,11 @@ b4 [20]  (W[i] maps layer input to output as y = x W^T + b).
 
 Input of one element T (2D, P^k, d = 2): [c_T, c_N0, c_N1, c_N2] with N_j the neighbour across
 local facet j (opposite vertex j), each flattened [d, Np], all divided by the scale s and
-multiplied by the element's orientation sign sigma (+1 for det J > 0, -1 otherwise: a point
-reflection maps the flow onto itself with w -> -w and swaps the two element orientations of a
-split-square mesh, so one network serves both).  The macro-step is w_T <- w_T + sigma s y.
+multiplied by the element's orientation sign sigma = sign of the x component of v_1 - v_0.
+The point reflection x -> 2c - x maps a solution of w_t + div(w (x) w) = 0 to the solution
+-w(2c - x), maps each element's coefficients to minus themselves in the reflected element's
+frame, and swaps the two triangles of a split square (their first edges point in opposite x
+directions), so one network serves both.  The macro-step is w_T <- w_T + sigma s y.
 """
 import numpy as np
 from scipy.special import erf
