@@ -11,27 +11,23 @@
 #include <vector>
 
 #include "../../include/dgconv.h"
+#include "internal.hpp"
 #include "conv_kernels.hpp"
 #include "mfma_kernels.hpp"
 #include "mesh.hpp"
 #include "refelem.hpp"
 
-namespace {
-
+namespace dgi {
 thread_local std::string g_err;
-
 dg_status fail(dg_status s, const std::string& msg) {
   g_err = msg;
   return s;
 }
+}  // namespace dgi
 
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(e_ == hipErrorOutOfMemory ? DG_ENOMEM : DG_EDEVICE,                   \
-                  std::string(#expr ": ") + hipGetErrorString(e_));                     \
-  } while (0)
+namespace {
+
+using dgi::fail;
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
@@ -39,33 +35,6 @@ constexpr int kMaxK2 = 6, kMaxK3 = 4;
 constexpr int kRedBlock = 256;
 
 }  // namespace
-
-struct dg_mesh {
-  dgmesh::Host h;
-  dgmesh::Tables t;
-  int device = 0;
-  double* d_tab = nullptr;
-  float* d_tab_f = nullptr;
-  double* d_jinv = nullptr;
-  float* d_jinv_f = nullptr;
-  double* d_absdet = nullptr;
-  int* d_nbr = nullptr;
-  int* d_elem_list = nullptr;
-  int* d_tile_type = nullptr;
-  int* d_type_tab = nullptr;
-  mutable void* d_work = nullptr;
-  mutable size_t work_bytes = 0;
-  double* d_partial = nullptr;  // reduction partials
-  int n_partial = 0;
-  bool on_device = false;
-  bool tables_lds = false;  // stage reference tables in LDS (where they fit) or read via SGPRs
-  bool fp64_mfma = false;   // FP64 operator on the matrix cores instead of the VALU kernel
-  // matrix-core path: 16-wide tiles and fragment tables per contraction engine
-  int* d_elem_list16 = nullptr;
-  int* d_tile_type16 = nullptr;
-  void* d_frag[3] = {nullptr, nullptr, nullptr};  // 0: f64, 1: fp16 x2, 2: bf16 x3
-  std::mutex mu;
-};
 
 namespace {
 
@@ -464,9 +433,11 @@ dg_status upload(const std::vector<T>& v, T** d) {
   return DG_OK;
 }
 
+}  // namespace
+
 // Device tables are uploaded on the first compute call (synchronously), to the device that
 // is current then; later calls must use the same device.
-dg_status ensure_device(const dg_mesh* cm) {
+dg_status dgi::ensure_device(const dg_mesh* cm) {
   dg_mesh* m = const_cast<dg_mesh*>(cm);
   std::lock_guard<std::mutex> lock(m->mu);
   int dev = 0;
@@ -495,6 +466,9 @@ dg_status ensure_device(const dg_mesh* cm) {
   return DG_OK;
 }
 
+namespace {
+using dgi::ensure_device;
+
 void free_mesh(dg_mesh* m) {
   if (!m) return;
   void* ptrs[] = {m->d_tab, m->d_tab_f, m->d_jinv, m->d_jinv_f, m->d_absdet, m->d_nbr,
@@ -509,7 +483,7 @@ void free_mesh(dg_mesh* m) {
 
 extern "C" {
 
-const char* dg_last_error(void) { return g_err.c_str(); }
+const char* dg_last_error(void) { return dgi::g_err.c_str(); }
 const char* dg_version(void) { return "dgconv 0.1 gfx950"; }
 
 dg_status dg_mesh_create(int dim, int k, int64_t n_vert, const double* xyz, int64_t n_elem,

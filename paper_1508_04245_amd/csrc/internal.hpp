@@ -1,0 +1,57 @@
+// Internal declarations shared by the translation units of libdgconv.so (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+
+#include "../../include/dgconv.h"
+#include "mesh.hpp"
+
+namespace dgi {
+
+// record an error message for dg_last_error() and return the status
+dg_status fail(dg_status s, const std::string& msg);
+
+}  // namespace dgi
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return dgi::fail(e_ == hipErrorOutOfMemory ? DG_ENOMEM : DG_EDEVICE,              \
+                       std::string(#expr ": ") + hipGetErrorString(e_));                \
+  } while (0)
+
+struct dg_mesh {
+  dgmesh::Host h;
+  dgmesh::Tables t;
+  int device = 0;
+  double* d_tab = nullptr;
+  float* d_tab_f = nullptr;
+  double* d_jinv = nullptr;
+  float* d_jinv_f = nullptr;
+  double* d_absdet = nullptr;
+  int* d_nbr = nullptr;
+  int* d_elem_list = nullptr;
+  int* d_tile_type = nullptr;
+  int* d_type_tab = nullptr;
+  mutable void* d_work = nullptr;
+  mutable size_t work_bytes = 0;
+  double* d_partial = nullptr;  // reduction partials
+  int n_partial = 0;
+  bool on_device = false;
+  bool tables_lds = false;  // stage reference tables in LDS (where they fit) or read via SGPRs
+  bool fp64_mfma = false;   // FP64 operator on the matrix cores instead of the VALU kernel
+  // matrix-core path: 16-wide tiles and fragment tables per contraction engine
+  int* d_elem_list16 = nullptr;
+  int* d_tile_type16 = nullptr;
+  void* d_frag[3] = {nullptr, nullptr, nullptr};  // 0: f64, 1: fp16 x2, 2: bf16 x3
+  std::mutex mu;
+};
+
+namespace dgi {
+// upload the mesh's device tables on first use (synchronous)
+dg_status ensure_device(const dg_mesh* m);
+}  // namespace dgi

@@ -56,9 +56,9 @@ class FourierField:
         self.amp = a / rms
 
     def __call__(self, x):
-        ph = TWO_PI * np.einsum("...j,mj->...m", x, self.kappa)
-        e = np.exp(1j * ph)
-        return np.real(np.einsum("...m,mi->...i", e, self.amp))
+        # Re sum_m a_m e^{i ph_m} = cos(ph) Re(a) - sin(ph) Im(a)
+        ph = TWO_PI * (x @ self.kappa.T)
+        return np.cos(ph) @ self.amp.real - np.sin(ph) @ self.amp.imag
 
 
 def shear_wave(x, t, c, xi, eta, A=1.0):
