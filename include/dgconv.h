@@ -131,6 +131,58 @@ enum { DG_RED_MAXVEL = 0, DG_RED_ENERGY = 1, DG_RED_MOMENTUM = 2, DG_RED_L2DIFF 
 dg_status dg_reduce(const dg_mesh* mesh, int what, const double* a, const double* b,
                     double* out_dev, void* stream);
 
+/* ---- Learned macro-step (2D, P3 elements): a per-element network replaces M substeps.
+ * Network 80 -> 256 -> 256 -> 256 -> 20 with erf-GELU; BF16 matrix-core kernels with FP32
+ * accumulation, FP32 master weights, Adam.  Flat FP32 parameters: W1 [256][80], b1 [256],
+ * W2 [256][256], b2, W3 [256][256], b3, W4 [20][256], b4 [20] (layer: y = x W^T + b).
+ * Input of element T: sigma_T / s [c_T, c_N0, c_N1, c_N2] (N_j across local facet j; each
+ * block [dim][n_basis]); s = max |w| over the volume points, sigma_T = sign of the x
+ * component of v1 - v0.  Output y_T is the remainder of the macro-step beyond forward Euler
+ * over tau = M dt, in units of s^3 tau^2 / h (h = the mesh's h_min):
+ *   w_T <- w_T + tau r(w)_T + sigma_T (s^3 tau^2 / h) y_T. */
+typedef struct dg_surrogate dg_surrogate;
+
+dg_status dg_surrogate_n_params(int64_t* n); /* 157460 */
+
+/* Create a network for this mesh (allocates device memory; parameters zero until loaded).
+ * M: substeps one macro-step replaces.  DG_EUNSUPPORTED unless dim = 2 and k = 3. */
+dg_status dg_surrogate_create(const dg_mesh* mesh, int M, dg_surrogate** out);
+void dg_surrogate_destroy(dg_surrogate* s);
+
+/* FP32 master parameters from / to the host (synchronous); load resets the Adam state. */
+dg_status dg_surrogate_load(dg_surrogate* s, const float* params_host, int64_t n);
+dg_status dg_surrogate_save(const dg_surrogate* s, float* params_host, int64_t n);
+
+/* Network inputs x_out (dev, FP32 [n][80]) and training targets t_out (dev, FP32 [n][20],
+ * sigma_T h / (s^3 tau^2) (w1 - w0 - tau r0)_T with r0 = r(w0)) of the elements elems (dev
+ * int32 [n], or NULL = all elements in order, then n = n_elem) of the FP64 states w, w0, w1,
+ * r0; scale: dev double, s; tau > 0. */
+dg_status dg_surrogate_features(const dg_surrogate* s, const double* w, const double* scale,
+                                const int32_t* elems, int64_t n, float* x_out, void* stream);
+dg_status dg_surrogate_targets(const dg_surrogate* s, const double* w0, const double* w1,
+                               const double* r0, const double* scale, double tau,
+                               const int32_t* elems, int64_t n, float* t_out, void* stream);
+
+/* y = net(x): x dev FP32 [batch][80], y dev FP32 [batch][20] (inputs rounded to BF16). */
+dg_status dg_surrogate_forward(dg_surrogate* s, const float* x, int64_t batch, float* y,
+                               void* stream);
+/* Mean-squared-error loss (dev float, may be NULL) and its gradient with respect to the
+ * parameters (dev FP32 [157460], may be NULL) for inputs x and targets t (dev FP32). */
+dg_status dg_surrogate_grad(dg_surrogate* s, const float* x, const float* t, int64_t batch,
+                            float* grad_out, float* loss_dev, void* stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias correction) with learning rate lr. */
+dg_status dg_surrogate_train_step(dg_surrogate* s, const float* x, const float* t,
+                                  int64_t batch, float lr, float* loss_dev, void* stream);
+
+/* One macro-step of M substeps of size dt on the FP64 state w (dev, in place, self-
+ * convection): candidate w~ = w + tau r(w) + sigma (s^3 tau^2 / h) net(...), tau = M dt,
+ * accepted when its trapezoid defect
+ * rho = ||w~ - w - (M dt / 2)(r(w) + r(w~))||_L2 / ||w~ - w||_L2 <= tol, else the M plain
+ * SSP-RK3 substeps are taken from w.  Synchronises the stream (the decision is made on the
+ * host); *accepted = 1 or 0, *rho_out = rho (may be NULL).  Uses workspace owned by s. */
+dg_status dg_macro_step(const dg_mesh* mesh, dg_surrogate* s, double* w, double dt, double tol,
+                        int* accepted, double* rho_out, void* stream);
+
 /* The library's reference basis on the unit simplex (host): vals [n_pts][n_basis] and,
  * if grads is not NULL, reference gradients [n_pts][n_basis][dim] at pts [n_pts][dim]. */
 dg_status dg_eval_basis(int dim, int k, int64_t n_pts, const double* pts, double* vals,

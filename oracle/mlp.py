@@ -16,7 +16,9 @@ multiplied by the element's orientation sign sigma = sign of the x component of 
 The point reflection x -> 2c - x maps a solution of w_t + div(w (x) w) = 0 to the solution
 -w(2c - x), maps each element's coefficients to minus themselves in the reflected element's
 frame, and swaps the two triangles of a split square (their first edges point in opposite x
-directions), so one network serves both.  The macro-step is w_T <- w_T + sigma s y.
+directions), so one network serves both.  The network output y_T is the remainder of the
+macro-step beyond forward Euler over tau = M dt, in units of s^3 tau^2 / h:
+w_T <- w_T + tau r(w)_T + sigma_T (s^3 tau^2 / h) y_T.
 """
 import numpy as np
 from scipy.special import erf

@@ -57,11 +57,22 @@ def lib():
         "dg_rk_substeps": [P, I, P, D, I, P, P, P],
         "dg_reduce": [P, I, P, P, P, P],
         "dg_eval_basis": [I, I, I64, P, P, P],
+        "dg_surrogate_n_params": [P],
+        "dg_surrogate_create": [P, I, P],
+        "dg_surrogate_destroy": [P],
+        "dg_surrogate_load": [P, P, I64],
+        "dg_surrogate_save": [P, P, I64],
+        "dg_surrogate_features": [P, P, P, P, I64, P, P],
+        "dg_surrogate_targets": [P, P, P, P, P, D, P, I64, P, P],
+        "dg_surrogate_forward": [P, P, I64, P, P],
+        "dg_surrogate_grad": [P, P, P, I64, P, P, P],
+        "dg_surrogate_train_step": [P, P, P, I64, ctypes.c_float, P, P],
+        "dg_macro_step": [P, P, P, D, D, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
-        f.restype = None if name == "dg_mesh_destroy" else ctypes.c_int
+        f.restype = None if name in ("dg_mesh_destroy", "dg_surrogate_destroy") else ctypes.c_int
     L.dg_last_error.restype = ctypes.c_char_p
     L.dg_version.restype = ctypes.c_char_p
     _lib = L
@@ -192,3 +203,84 @@ class Mesh:
                                None if b is None else _dev(b, torch.float64),
                                _dev(out, torch.float64), _stream(stream)))
         return out
+
+
+class Surrogate:
+    """The learned macro-step network of a 2D P3 mesh (dg_surrogate)."""
+
+    def __init__(self, mesh, M=8):
+        self.mesh = mesh
+        self.M = M
+        h = ctypes.c_void_p()
+        _check(lib().dg_surrogate_create(mesh._h, M, ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_int64()
+        _check(lib().dg_surrogate_n_params(ctypes.byref(n)))
+        self.n_params = n.value
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.dg_surrogate_destroy(self._h)
+            self._h = None
+
+    def load(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(lib().dg_surrogate_load(self._h, _ptr(p), p.size))
+
+    def save(self):
+        p = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().dg_surrogate_save(self._h, _ptr(p), p.size))
+        return p
+
+    def features(self, w, scale, elems=None, out=None, stream=None):
+        import torch
+        n = self.mesh.E if elems is None else elems.numel()
+        if out is None:
+            out = torch.empty((n, 80), dtype=torch.float32, device=w.device)
+        _check(lib().dg_surrogate_features(self._h, _dev(w, torch.float64), _dev(scale, torch.float64),
+                                           None if elems is None else _dev(elems, torch.int32), n,
+                                           _dev(out, torch.float32), _stream(stream)))
+        return out
+
+    def targets(self, w0, w1, r0, scale, tau, elems=None, out=None, stream=None):
+        import torch
+        n = self.mesh.E if elems is None else elems.numel()
+        if out is None:
+            out = torch.empty((n, 20), dtype=torch.float32, device=w0.device)
+        _check(lib().dg_surrogate_targets(self._h, _dev(w0, torch.float64), _dev(w1, torch.float64),
+                                          _dev(r0, torch.float64), _dev(scale, torch.float64),
+                                          float(tau),
+                                          None if elems is None else _dev(elems, torch.int32), n,
+                                          _dev(out, torch.float32), _stream(stream)))
+        return out
+
+    def forward(self, x, stream=None):
+        import torch
+        y = torch.empty((x.shape[0], 20), dtype=torch.float32, device=x.device)
+        _check(lib().dg_surrogate_forward(self._h, _dev(x, torch.float32), x.shape[0],
+                                          _dev(y, torch.float32), _stream(stream)))
+        return y
+
+    def grad(self, x, t, stream=None):
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        loss = torch.zeros(1, dtype=torch.float32, device=x.device)
+        _check(lib().dg_surrogate_grad(self._h, _dev(x, torch.float32), _dev(t, torch.float32),
+                                       x.shape[0], _dev(g, torch.float32), _dev(loss, torch.float32),
+                                       _stream(stream)))
+        return loss, g
+
+    def train_step(self, x, t, lr, loss=None, stream=None):
+        _check(lib().dg_surrogate_train_step(self._h, _dev(x), _dev(t), x.shape[0], float(lr),
+                                             None if loss is None else _dev(loss), _stream(stream)))
+        return loss
+
+    def macro_step(self, w, dt, tol, stream=None):
+        """One macro-step in place on w; returns (accepted, rho)."""
+        import torch
+        acc = ctypes.c_int()
+        rho = ctypes.c_double()
+        _check(lib().dg_macro_step(self.mesh._h, self._h, _dev(w, torch.float64), float(dt),
+                                   float(tol), ctypes.byref(acc), ctypes.byref(rho),
+                                   _stream(stream)))
+        return bool(acc.value), rho.value

@@ -1,0 +1,656 @@
+// Learned macro-step for the explicit substeps of the propagation problem: a per-element
+// network (own plus face-neighbour coefficients -> increment over M substeps), trained and
+// run with hand-written BF16 matrix-core kernels (FP32 accumulation, FP32 master weights),
+// with an a-posteriori defect check and the plain SSP-RK3 substeps as fallback.
+//
+// Network 80 -> 256 -> 256 -> 256 -> 20, erf GELU, flat FP32 parameters in the order
+// W1 [256,80], b1, W2 [256,256], b2, W3 [256,256], b3, W4 [20,256], b4 (y = x W^T + b).
+// Input of element T: sigma_T / s * [c_T, c_N0, c_N1, c_N2] (N_j across local facet j), with
+// s = max|w| over the volume points and sigma_T = sign of the x component of v1 - v0 (the two
+// triangles of a split square are point reflections of each other, and the reflection maps
+// the flow to itself with w -> -w).  Macro-step: w_T <- w_T + sigma_T s y_T.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace {
+
+using dgi::fail;
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+constexpr int kIn = 80, kHid = 256, kOut = 20;
+constexpr int64_t kParams = (int64_t)kHid * kIn + kHid + 2 * ((int64_t)kHid * kHid + kHid) +
+                            (int64_t)kOut * kHid + kOut;
+// offsets of the layers in the flat parameter vector
+constexpr int64_t kOffW[4] = {0, kHid * kIn + kHid, kHid * kIn + kHid + kHid * kHid + kHid,
+                              kHid * kIn + kHid + 2 * (kHid * kHid + kHid)};
+constexpr int kFanIn[4] = {kIn, kHid, kHid, kHid};
+constexpr int kFanOut[4] = {kHid, kHid, kHid, kOut};
+
+__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_d(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+         z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+// ------------------------------------------------------------------ GEMM
+// C(m,n) = sum_k A(m,k) B(k,n) over BF16 operands with FP32 accumulation on the matrix cores
+// (v_mfma_f32_16x16x16_bf16).  A(m,k) = A[m am + k ak], B(k,n) = B[k bk + n bn].  A wave
+// computes a 32x32 block (2x2 MFMA tiles), a workgroup of 4 waves a 64x64 block.
+enum Epi { EPI_BIAS = 0, EPI_BIAS_GELU = 1, EPI_GELU_BWD = 2, EPI_STORE = 3 };
+struct GemmArgs {
+  int M, N, K;
+  const uint16_t* A;
+  int64_t am, ak;
+  const uint16_t* B;
+  int64_t bk, bn;
+  const float* bias;  // [N] (EPI_BIAS, EPI_BIAS_GELU)
+  const float* Z;     // pre-activations [M][ldz] (EPI_GELU_BWD)
+  int64_t ldz;
+  float* Cf;          // FP32 result [M][ldc] or nullptr
+  uint16_t* Cb;       // BF16 result [M][ldc] or nullptr (after the activation)
+  int64_t ldc;
+};
+
+__device__ __forceinline__ s4 load4(const uint16_t* p, int64_t row, int64_t rs, int k0, int64_t ks,
+                                    int rows, int K) {
+  s4 v = {0, 0, 0, 0};
+  if (row >= rows) return v;
+  const uint16_t* q = p + row * rs;
+  if (ks == 1 && k0 + 3 < K && ((((uintptr_t)(q + k0)) & 7) == 0)) {
+    const uint2 u = *(const uint2*)(q + k0);
+    v[0] = (short)(u.x & 0xffff); v[1] = (short)(u.x >> 16);
+    v[2] = (short)(u.y & 0xffff); v[3] = (short)(u.y >> 16);
+    return v;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] = (k0 + j < K) ? (short)q[(int64_t)(k0 + j) * ks] : (short)0;
+  return v;
+}
+
+template <int EPI>
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g4 = lane >> 4, c = lane & 15;
+  const int m0 = blockIdx.y * 64 + 32 * (w >> 1);
+  const int n0 = blockIdx.x * 64 + 32 * (w & 1);
+  f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < g.K; k0 += 16) {
+    const int kk = k0 + 4 * g4;
+    s4 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = load4(g.A, m0 + 16 * i + c, g.am, kk, g.ak, g.M, g.K);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = load4(g.B, n0 + 16 * j + c, g.bn, kk, g.bk, g.N, g.K);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + 16 * i + 4 * g4 + r, n = n0 + 16 * j + c;
+        if (m >= g.M || n >= g.N) continue;
+        float v = acc[i][j][r];
+        const int64_t o = (int64_t)m * g.ldc + n;
+        if constexpr (EPI == EPI_BIAS || EPI == EPI_BIAS_GELU) v += g.bias[n];
+        if constexpr (EPI == EPI_BIAS_GELU) {
+          if (g.Cf) g.Cf[o] = v;  // pre-activation, kept for the backward pass
+          g.Cb[o] = f2bf(gelu(v));
+        } else if constexpr (EPI == EPI_GELU_BWD) {
+          v *= gelu_d(g.Z[(int64_t)m * g.ldz + n]);
+          if (g.Cf) g.Cf[o] = v;
+          g.Cb[o] = f2bf(v);
+        } else {
+          if (g.Cf) g.Cf[o] = v;
+          if (g.Cb) g.Cb[o] = f2bf(v);
+        }
+      }
+}
+
+template <int EPI>
+hipError_t gemm(const GemmArgs& g, hipStream_t s) {
+  const dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+  hipLaunchKernelGGL(gemm_kernel<EPI>, grid, dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ elementwise / reductions
+__global__ void cast_bf16_kernel(int64_t n, const float* x, uint16_t* y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = f2bf(x[i]);
+}
+
+// dy = 2 (y - t) / (B O) (FP32 and BF16), and per-block partial sums of (y - t)^2
+__global__ void __launch_bounds__(256)
+mse_kernel(int64_t n, float inv, const float* y, const float* t, float* dyf, uint16_t* dyb,
+           float* partial) {
+  __shared__ float sh[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  float e2 = 0.f;
+  if (i < n) {
+    const float d = y[i] - t[i];
+    e2 = d * d;
+    const float g = 2.0f * d * inv;
+    dyf[i] = g;
+    dyb[i] = f2bf(g);
+  }
+  sh[threadIdx.x] = e2;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) sum_kernel(int n, const float* partial, float scale, float* out) {
+  __shared__ float sh[256];
+  float v = 0.f;
+  for (int i = threadIdx.x; i < n; i += 256) v += partial[i];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0] * scale;
+}
+
+// bias gradients: db[n] = sum_m D[m][n], one thread per column, fixed order
+__global__ void colsum_kernel(int M, int N, const float* D, float* db) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (int m = 0; m < M; ++m) s += D[(int64_t)m * N + n];
+  db[n] = s;
+}
+
+// Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias correction) on the FP32 master weights,
+// followed by the BF16 copy the kernels read
+__global__ void adam_kernel(int64_t n, float lr, float c1, float c2, float* p, float* m, float* v,
+                            const float* g, uint16_t* pb) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = 0.9f * m[i] + 0.1f * gi;
+  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+  p[i] = pi;
+  pb[i] = f2bf(pi);
+}
+
+// network inputs: x[b][0..79] = sigma_T / s [c_T, c_N0, c_N1, c_N2], T = elems[b] (or b)
+__global__ void features_kernel(int64_t n, int dim, int np, const int32_t* elems,
+                                const int32_t* nbr, const float* sigma, const double* w,
+                                const double* scale, float* xf, uint16_t* xb) {
+  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (b >= n) return;
+  const int64_t T = elems ? elems[b] : b;
+  const int per = dim * np;
+  const double f = sigma[T] / scale[0];
+  for (int j = lane; j < (dim + 2) * per; j += 64) {
+    const int blk = j / per, off = j % per;
+    const int64_t S = blk == 0 ? T : nbr[T * (dim + 1) + blk - 1];
+    const float v = (float)(w[S * per + off] * f);
+    if (xf) xf[b * (int64_t)((dim + 2) * per) + j] = v;
+    if (xb) xb[b * (int64_t)((dim + 2) * per) + j] = f2bf(v);
+  }
+}
+
+// The network predicts the remainder of the macro-step beyond forward Euler over the macro
+// interval tau = M dt, in units of s^3 tau^2 / h (the size of that remainder for a flow of
+// speed s resolved on elements of size h):
+//   w(t + tau) = w + tau r(w) + sigma_T (s^3 tau^2 / h) y_T
+// training targets: t[b][j] = sigma_T h / (s^3 tau^2) (w1 - w0 - tau r0)_T[j]
+__global__ void targets_kernel(int64_t n, int per, const int32_t* elems, const float* sigma,
+                               const double* w0, const double* w1, const double* r0,
+                               const double* scale, double tau, double h, float* t) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n * per) return;
+  const int64_t b = i / per, j = i % per;
+  const int64_t T = elems ? elems[b] : b;
+  const double s = scale[0];
+  const double unit = s * s * s * tau * tau / h;
+  const int64_t k = T * per + j;
+  t[i] = (float)((w1[k] - w0[k] - tau * r0[k]) * sigma[T] / unit);
+}
+
+// candidate: wt = w + tau r0 + sigma_T (s^3 tau^2 / h) y_T
+__global__ void update_kernel(int64_t E, int per, const float* sigma, const double* w,
+                              const double* r0, const float* y, const double* scale, double tau,
+                              double h, double* wt) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= E * per) return;
+  const int64_t T = i / per;
+  const double s = scale[0];
+  wt[i] = w[i] + tau * r0[i] + (double)sigma[T] * (s * s * s * tau * tau / h) * (double)y[i];
+}
+
+// trapezoid defect of the macro-step: num = sum |J| |wt - w - h/2 (r0 + r1)|^2,
+// den = sum |J| |wt - w|^2, per block
+__global__ void __launch_bounds__(256)
+defect_kernel(int64_t E, int per, double half_T, const double* absdet, const double* w,
+              const double* wt, const double* r0, const double* r1, double* partial) {
+  __shared__ double sh[256][2];
+  const int64_t T = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double a = 0, b = 0;
+  if (T < E) {
+    for (int j = 0; j < per; ++j) {
+      const int64_t i = T * per + j;
+      const double d = wt[i] - w[i];
+      const double e = d - half_T * (r0[i] + r1[i]);
+      a = fma(e, e, a);
+      b = fma(d, d, b);
+    }
+    a *= absdet[T];
+    b *= absdet[T];
+  }
+  sh[threadIdx.x][0] = a;
+  sh[threadIdx.x][1] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sh[threadIdx.x][0] += sh[threadIdx.x + s][0];
+      sh[threadIdx.x][1] += sh[threadIdx.x + s][1];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x * 2] = sh[0][0];
+    partial[blockIdx.x * 2 + 1] = sh[0][1];
+  }
+}
+
+__global__ void __launch_bounds__(256) defect_final_kernel(int n, const double* partial, double* rho) {
+  __shared__ double sh[256][2];
+  double a = 0, b = 0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    a += partial[2 * i];
+    b += partial[2 * i + 1];
+  }
+  sh[threadIdx.x][0] = a;
+  sh[threadIdx.x][1] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sh[threadIdx.x][0] += sh[threadIdx.x + s][0];
+      sh[threadIdx.x][1] += sh[threadIdx.x + s][1];
+    }
+    __syncthreads();
+  }
+  // non-finite sums give a non-finite defect (rejected); no change predicted gives an
+  // infinite defect unless the operator vanishes too
+  if (threadIdx.x == 0) {
+    const double a = sh[0][0], b = sh[0][1];
+    if (!isfinite(a) || !isfinite(b)) rho[0] = NAN;
+    else rho[0] = b > 0 ? sqrt(a / b) : (a > 0 ? INFINITY : 0.0);
+  }
+}
+
+inline int nblk(int64_t n, int b = 256) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+
+struct dg_surrogate {
+  int M = 8, dim = 2, np = 10, device = 0;
+  double hmesh = 0;           // element size of the mesh (smallest facet measure)
+  int64_t E = 0;
+  float* master = nullptr;    // FP32 parameters
+  uint16_t* wbf = nullptr;    // BF16 copy
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  float* grad = nullptr;
+  int64_t t = 0;              // Adam step count
+  float* sigma = nullptr;     // [E] orientation signs
+  int32_t* nbr = nullptr;     // [E][dim+1] (device copy of the mesh's)
+  // batch workspace
+  int64_t cap = 0;
+  uint16_t* xb = nullptr;     // [cap][80]
+  float* z[3] = {nullptr, nullptr, nullptr};    // pre-activations [cap][256]
+  uint16_t* h[3] = {nullptr, nullptr, nullptr}; // activations (BF16)
+  float* y = nullptr;         // [cap][20]
+  float* dyf = nullptr;       // [cap][256] FP32 upstream gradient (bias sums)
+  uint16_t* dyb = nullptr;    // [cap][256] BF16 upstream gradient
+  uint16_t* dyb2 = nullptr;   // [cap][256] second BF16 buffer
+  float* partial = nullptr;   // [nblk(cap*20)]
+  // macro-step workspace (FP64 states) and scale
+  double* mwork = nullptr;    // 5 states: wt, r0, r1 (rk work aliases r0, r1)
+  double* scale = nullptr;    // [4]
+  double* dpart = nullptr;    // defect partials
+  double* rho = nullptr;
+};
+
+namespace {
+
+dg_status ensure_cap(dg_surrogate* s, int64_t B) {
+  if (B <= s->cap) return DG_OK;
+  void* ptrs[] = {s->xb, s->z[0], s->z[1], s->z[2], s->h[0], s->h[1], s->h[2], s->y, s->dyf,
+                  s->dyb, s->dyb2, s->partial};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  s->cap = 0;
+  HIP_TRY(hipMalloc((void**)&s->xb, B * kIn * 2));
+  for (int l = 0; l < 3; ++l) {
+    HIP_TRY(hipMalloc((void**)&s->z[l], B * kHid * 4));
+    HIP_TRY(hipMalloc((void**)&s->h[l], B * kHid * 2));
+  }
+  HIP_TRY(hipMalloc((void**)&s->y, B * kOut * 4));
+  HIP_TRY(hipMalloc((void**)&s->dyf, B * kHid * 4));
+  HIP_TRY(hipMalloc((void**)&s->dyb, B * kHid * 2));
+  HIP_TRY(hipMalloc((void**)&s->dyb2, B * kHid * 2));
+  HIP_TRY(hipMalloc((void**)&s->partial, (nblk(B * kOut) + 1) * 4));
+  s->cap = B;
+  return DG_OK;
+}
+
+// forward over s->xb (BF16 inputs) for B rows; keeps pre-activations when train
+dg_status forward(dg_surrogate* s, int64_t B, bool train, hipStream_t st) {
+  const uint16_t* in = s->xb;
+  int fin = kIn;
+  for (int l = 0; l < 3; ++l) {
+    GemmArgs g{};
+    g.M = (int)B; g.N = kHid; g.K = fin;
+    g.A = in; g.am = fin; g.ak = 1;
+    g.B = s->wbf + kOffW[l]; g.bk = 1; g.bn = fin;
+    g.bias = s->master + kOffW[l] + (int64_t)kHid * fin;
+    g.Cf = train ? s->z[l] : nullptr; g.Cb = s->h[l]; g.ldc = kHid;
+    HIP_TRY(gemm<EPI_BIAS_GELU>(g, st));
+    in = s->h[l];
+    fin = kHid;
+  }
+  GemmArgs g{};
+  g.M = (int)B; g.N = kOut; g.K = kHid;
+  g.A = in; g.am = kHid; g.ak = 1;
+  g.B = s->wbf + kOffW[3]; g.bk = 1; g.bn = kHid;
+  g.bias = s->master + kOffW[3] + (int64_t)kOut * kHid;
+  g.Cf = s->y; g.ldc = kOut;
+  HIP_TRY(gemm<EPI_BIAS>(g, st));
+  return DG_OK;
+}
+
+// loss and gradient into s->grad for targets t (FP32 [B][20]); forward must have run (train)
+dg_status backward(dg_surrogate* s, int64_t B, const float* t, float* loss_dev, hipStream_t st) {
+  const int64_t n = B * kOut;
+  hipLaunchKernelGGL(mse_kernel, dim3(nblk(n)), dim3(256), 0, st, n, 1.0f / (float)n, s->y, t,
+                     s->dyf, s->dyb, s->partial);
+  HIP_TRY(hipGetLastError());
+  if (loss_dev) {
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, st, nblk(n), s->partial,
+                       1.0f / (float)n, loss_dev);
+    HIP_TRY(hipGetLastError());
+  }
+  uint16_t* dcur = s->dyb;   // BF16 gradient w.r.t. the current layer's output (pre-activation)
+  uint16_t* dnext = s->dyb2;
+  for (int l = 3; l >= 0; --l) {
+    const int fout = kFanOut[l], fin = kFanIn[l];
+    const uint16_t* hin = l == 0 ? s->xb : s->h[l - 1];
+    // dW = D^T H_in : M = fout, N = fin, K = B
+    GemmArgs g{};
+    g.M = fout; g.N = fin; g.K = (int)B;
+    g.A = dcur; g.am = 1; g.ak = fout;
+    g.B = hin; g.bk = fin; g.bn = 1;
+    g.Cf = s->grad + kOffW[l]; g.ldc = fin;
+    HIP_TRY(gemm<EPI_STORE>(g, st));
+    // db = column sums of the FP32 gradient
+    hipLaunchKernelGGL(colsum_kernel, dim3(nblk(fout)), dim3(256), 0, st, (int)B, fout, s->dyf,
+                       s->grad + kOffW[l] + (int64_t)fout * fin);
+    HIP_TRY(hipGetLastError());
+    if (l == 0) break;
+    // D_prev = (D W) * gelu'(z_prev) : M = B, N = fin, K = fout
+    GemmArgs b{};
+    b.M = (int)B; b.N = fin; b.K = fout;
+    b.A = dcur; b.am = fout; b.ak = 1;
+    b.B = s->wbf + kOffW[l]; b.bk = fin; b.bn = 1;
+    b.Z = s->z[l - 1]; b.ldz = kHid;
+    b.Cf = s->dyf; b.Cb = dnext; b.ldc = fin;
+    HIP_TRY(gemm<EPI_GELU_BWD>(b, st));
+    std::swap(dcur, dnext);
+  }
+  return DG_OK;
+}
+
+void free_surrogate(dg_surrogate* s) {
+  if (!s) return;
+  void* ptrs[] = {s->master, s->wbf, s->adam_m, s->adam_v, s->grad, s->sigma, s->nbr, s->xb,
+                  s->z[0], s->z[1], s->z[2], s->h[0], s->h[1], s->h[2], s->y, s->dyf, s->dyb,
+                  s->dyb2, s->partial, s->mwork, s->scale, s->dpart, s->rho};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete s;
+}
+
+bool al16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+dg_status dg_surrogate_n_params(int64_t* n) {
+  if (!n) return fail(DG_EINVAL, "null pointer");
+  *n = kParams;
+  return DG_OK;
+}
+
+dg_status dg_surrogate_create(const dg_mesh* m, int M, dg_surrogate** out) {
+  if (!m || !out) return fail(DG_EINVAL, "null pointer");
+  if (M < 1) return fail(DG_EINVAL, "M must be >= 1");
+  if ((m->h.dim + 2) * m->h.dim * m->h.np != kIn || m->h.dim * m->h.np != kOut)
+    return fail(DG_EUNSUPPORTED, "the network is built for 2D P3 elements (80 inputs, 20 outputs)");
+  dg_status st = dgi::ensure_device(m);
+  if (st != DG_OK) return st;
+  dg_surrogate* s = new (std::nothrow) dg_surrogate();
+  if (!s) return fail(DG_ENOMEM, "host allocation");
+  s->M = M;
+  s->dim = m->h.dim;
+  s->np = m->h.np;
+  s->E = m->h.E;
+  s->hmesh = m->h.hmin;
+  (void)hipGetDevice(&s->device);
+  std::vector<float> sig(s->E);
+  const int nv = s->dim + 1;
+  for (int64_t t = 0; t < s->E; ++t) {
+    const double dx = m->h.X[(t * nv + 1) * s->dim] - m->h.X[(t * nv) * s->dim];
+    sig[t] = dx < 0 ? -1.0f : 1.0f;
+  }
+  auto body = [&]() -> dg_status {
+    HIP_TRY(hipMalloc((void**)&s->master, kParams * 4));
+    HIP_TRY(hipMalloc((void**)&s->wbf, kParams * 2));
+    HIP_TRY(hipMalloc((void**)&s->adam_m, kParams * 4));
+    HIP_TRY(hipMalloc((void**)&s->adam_v, kParams * 4));
+    HIP_TRY(hipMalloc((void**)&s->grad, kParams * 4));
+    HIP_TRY(hipMemset(s->master, 0, kParams * 4));
+    HIP_TRY(hipMemset(s->wbf, 0, kParams * 2));
+    HIP_TRY(hipMemset(s->adam_m, 0, kParams * 4));
+    HIP_TRY(hipMemset(s->adam_v, 0, kParams * 4));
+    HIP_TRY(hipMalloc((void**)&s->sigma, s->E * 4));
+    HIP_TRY(hipMemcpy(s->sigma, sig.data(), s->E * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc((void**)&s->nbr, m->h.nbr.size() * 4));
+    HIP_TRY(hipMemcpy(s->nbr, m->h.nbr.data(), m->h.nbr.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc((void**)&s->scale, 4 * 8));
+    HIP_TRY(hipMalloc((void**)&s->rho, 8));
+    HIP_TRY(hipMalloc((void**)&s->dpart, (nblk(s->E) + 1) * 2 * 8));
+    HIP_TRY(hipMalloc((void**)&s->mwork, 3 * (size_t)s->E * s->dim * s->np * 8 + 64));
+    return DG_OK;
+  };
+  st = body();
+  if (st != DG_OK) {
+    std::string keep = dg_last_error();
+    free_surrogate(s);
+    return fail(st, keep);
+  }
+  *out = s;
+  return DG_OK;
+}
+
+void dg_surrogate_destroy(dg_surrogate* s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  free_surrogate(s);
+}
+
+dg_status dg_surrogate_load(dg_surrogate* s, const float* params, int64_t n) {
+  if (!s || !params) return fail(DG_EINVAL, "null pointer");
+  if (n != kParams) return fail(DG_EINVAL, "parameter count mismatch");
+  std::vector<uint16_t> b(n);
+  for (int64_t i = 0; i < n; ++i) {
+    uint32_t u;
+    std::memcpy(&u, &params[i], 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    b[i] = (uint16_t)(u >> 16);
+  }
+  HIP_TRY(hipMemcpy(s->master, params, n * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(s->wbf, b.data(), n * 2, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(s->adam_m, 0, n * 4));
+  HIP_TRY(hipMemset(s->adam_v, 0, n * 4));
+  s->t = 0;
+  return DG_OK;
+}
+
+dg_status dg_surrogate_save(const dg_surrogate* s, float* params, int64_t n) {
+  if (!s || !params) return fail(DG_EINVAL, "null pointer");
+  if (n != kParams) return fail(DG_EINVAL, "parameter count mismatch");
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(params, s->master, n * 4, hipMemcpyDeviceToHost));
+  return DG_OK;
+}
+
+dg_status dg_surrogate_features(const dg_surrogate* s, const double* w, const double* scale,
+                                const int32_t* elems, int64_t n, float* x_out, void* stream) {
+  if (!s || !w || !scale || !x_out) return fail(DG_EINVAL, "null pointer");
+  if (n < 0 || (!elems && n != s->E)) return fail(DG_EINVAL, "n must be n_elem when elems is NULL");
+  if (n == 0) return DG_OK;
+  hipLaunchKernelGGL(features_kernel, dim3(nblk(n, 4)), dim3(256), 0, (hipStream_t)stream, n,
+                     s->dim, s->np, elems, s->nbr, s->sigma, w, scale, x_out, (uint16_t*)nullptr);
+  HIP_TRY(hipGetLastError());
+  return DG_OK;
+}
+
+dg_status dg_surrogate_targets(const dg_surrogate* s, const double* w0, const double* w1,
+                               const double* r0, const double* scale, double tau,
+                               const int32_t* elems, int64_t n, float* t_out, void* stream) {
+  if (!s || !w0 || !w1 || !r0 || !scale || !t_out) return fail(DG_EINVAL, "null pointer");
+  if (!(tau > 0) || !std::isfinite(tau)) return fail(DG_EINVAL, "tau must be positive");
+  if (n < 0 || (!elems && n != s->E)) return fail(DG_EINVAL, "n must be n_elem when elems is NULL");
+  if (n == 0) return DG_OK;
+  const int per = s->dim * s->np;
+  hipLaunchKernelGGL(targets_kernel, dim3(nblk(n * per)), dim3(256), 0, (hipStream_t)stream, n,
+                     per, elems, s->sigma, w0, w1, r0, scale, tau, s->hmesh, t_out);
+  HIP_TRY(hipGetLastError());
+  return DG_OK;
+}
+
+dg_status dg_surrogate_forward(dg_surrogate* s, const float* x, int64_t B, float* y, void* stream) {
+  if (!s || !x || !y) return fail(DG_EINVAL, "null pointer");
+  if (B <= 0) return fail(DG_EINVAL, "batch must be positive");
+  dg_status st = ensure_cap(s, B);
+  if (st != DG_OK) return st;
+  const hipStream_t hs = (hipStream_t)stream;
+  hipLaunchKernelGGL(cast_bf16_kernel, dim3(nblk(B * kIn)), dim3(256), 0, hs, B * kIn, x, s->xb);
+  HIP_TRY(hipGetLastError());
+  if ((st = forward(s, B, false, hs)) != DG_OK) return st;
+  HIP_TRY(hipMemcpyAsync(y, s->y, B * kOut * 4, hipMemcpyDeviceToDevice, hs));
+  return DG_OK;
+}
+
+dg_status dg_surrogate_grad(dg_surrogate* s, const float* x, const float* t, int64_t B,
+                            float* grad_out, float* loss_dev, void* stream) {
+  if (!s || !x || !t) return fail(DG_EINVAL, "null pointer");
+  if (B <= 0) return fail(DG_EINVAL, "batch must be positive");
+  dg_status st = ensure_cap(s, B);
+  if (st != DG_OK) return st;
+  const hipStream_t hs = (hipStream_t)stream;
+  hipLaunchKernelGGL(cast_bf16_kernel, dim3(nblk(B * kIn)), dim3(256), 0, hs, B * kIn, x, s->xb);
+  HIP_TRY(hipGetLastError());
+  if ((st = forward(s, B, true, hs)) != DG_OK) return st;
+  if ((st = backward(s, B, t, loss_dev, hs)) != DG_OK) return st;
+  if (grad_out) HIP_TRY(hipMemcpyAsync(grad_out, s->grad, kParams * 4, hipMemcpyDeviceToDevice, hs));
+  return DG_OK;
+}
+
+dg_status dg_surrogate_train_step(dg_surrogate* s, const float* x, const float* t, int64_t B,
+                                  float lr, float* loss_dev, void* stream) {
+  if (!(lr >= 0) || !std::isfinite(lr)) return fail(DG_EINVAL, "lr must be finite and >= 0");
+  dg_status st = dg_surrogate_grad(s, x, t, B, nullptr, loss_dev, stream);
+  if (st != DG_OK) return st;
+  s->t += 1;
+  const float c1 = 1.0f - std::pow(0.9f, (float)s->t), c2 = 1.0f - std::pow(0.999f, (float)s->t);
+  hipLaunchKernelGGL(adam_kernel, dim3(nblk(kParams)), dim3(256), 0, (hipStream_t)stream,
+                     kParams, lr, c1, c2, s->master, s->adam_m, s->adam_v, s->grad, s->wbf);
+  HIP_TRY(hipGetLastError());
+  return DG_OK;
+}
+
+dg_status dg_macro_step(const dg_mesh* m, dg_surrogate* s, double* w, double dt, double tol,
+                        int* accepted, double* rho_out, void* stream) {
+  if (!m || !s || !w || !accepted) return fail(DG_EINVAL, "null pointer");
+  if (!al16(w)) return fail(DG_EINVAL, "w must be 16-byte aligned");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be positive and finite");
+  if (m->h.E != s->E) return fail(DG_EINVAL, "surrogate was created for another mesh");
+  const hipStream_t hs = (hipStream_t)stream;
+  const int64_t E = s->E;
+  const int per = s->dim * s->np;
+  const size_t n_state = (size_t)E * per;
+  double* wt = s->mwork;
+  double* r0 = wt + n_state;
+  double* r1 = r0 + n_state;
+  dg_status st = ensure_cap(s, E);
+  if (st != DG_OK) return st;
+  // r0 = r(w), scale s = max |w|, network inputs, forward pass, candidate, r1 = r(w~)
+  const double tau = s->M * dt;
+  if ((st = dg_convection_apply(m, DG_FP64, w, nullptr, r0, stream)) != DG_OK) return st;
+  if ((st = dg_reduce(m, DG_RED_MAXVEL, w, nullptr, s->scale, stream)) != DG_OK) return st;
+  hipLaunchKernelGGL(features_kernel, dim3(nblk(E, 4)), dim3(256), 0, hs, E, s->dim, s->np,
+                     (const int32_t*)nullptr, s->nbr, s->sigma, w, s->scale, (float*)nullptr, s->xb);
+  HIP_TRY(hipGetLastError());
+  if ((st = forward(s, E, false, hs)) != DG_OK) return st;
+  hipLaunchKernelGGL(update_kernel, dim3(nblk(E * per)), dim3(256), 0, hs, E, per, s->sigma, w,
+                     r0, s->y, s->scale, tau, s->hmesh, wt);
+  HIP_TRY(hipGetLastError());
+  // a-posteriori check: trapezoid defect over the macro interval
+  if ((st = dg_convection_apply(m, DG_FP64, wt, nullptr, r1, stream)) != DG_OK) return st;
+  hipLaunchKernelGGL(defect_kernel, dim3(nblk(E)), dim3(256), 0, hs, E, per, 0.5 * s->M * dt,
+                     m->d_absdet, w, wt, r0, r1, s->dpart);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(defect_final_kernel, dim3(1), dim3(256), 0, hs, nblk(E), s->dpart, s->rho);
+  HIP_TRY(hipGetLastError());
+  double rho = 0;
+  HIP_TRY(hipMemcpyAsync(&rho, s->rho, 8, hipMemcpyDeviceToHost, hs));
+  HIP_TRY(hipStreamSynchronize(hs));
+  if (rho_out) *rho_out = rho;
+  if (std::isfinite(rho) && rho <= tol) {
+    HIP_TRY(hipMemcpyAsync(w, wt, n_state * 8, hipMemcpyDeviceToDevice, hs));
+    *accepted = 1;
+  } else {
+    // fallback: the plain substeps from w (r0, r1 serve as the Runge-Kutta work buffers)
+    if ((st = dg_rk_substeps(m, DG_FP64, w, dt, s->M, nullptr, r0, stream)) != DG_OK) return st;
+    *accepted = 0;
+  }
+  return DG_OK;
+}
+
+}  // extern "C"

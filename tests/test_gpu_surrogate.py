@@ -1,0 +1,147 @@
+"""GPU checks of the learned macro-step kernels against the FP64 network oracle.
+
+Tolerances: the network runs on BF16 operands (8 significant bits, unit roundoff 2^-9 = 2e-3)
+with FP32 accumulation; through four layers the relative error of outputs and gradients is a
+few 2^-9, so the bar is 3e-2 relative L2 (and 0.999 cosine for the gradient direction).
+"""
+import numpy as np
+import pytest
+
+from gpu_common import say
+from oracle import mlp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import paper_1508_04245_amd as dg
+    from paper_1508_04245_amd import surrogate as S
+    assert torch.cuda.is_available()
+    mesh = dg.Mesh.box(2, 16, 3)
+    sur = dg.Surrogate(mesh, M=8)
+    return dg, S, mesh, sur
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_features_and_targets(env):
+    dg, S, mesh, sur = env
+    say("case surrogate features")
+    w = S.initial_state(mesh, 3)
+    wd = torch.tensor(w, device="cuda")
+    scale = torch.tensor([1.7], dtype=torch.float64, device="cuda")
+    elems = torch.tensor([0, 5, 17, mesh.E - 1], dtype=torch.int32, device="cuda")
+    x = sur.features(wd, scale, elems).cpu().numpy()
+    nb, _ = mesh.neighbors()
+    X = mesh.vertices()
+    sign = np.where(X[:, 1, 0] - X[:, 0, 0] < 0, -1.0, 1.0)
+    ref = mlp.features(w, nb, sign, 1.7, elems.cpu().numpy())
+    assert np.abs(x - ref).max() <= 1e-6 * np.abs(ref).max()
+    w1 = w * 1.01 + 0.003
+    r0 = w * 0.5 - 0.1
+    tau, h = 0.02, mesh.info["h_min"]
+    t = sur.targets(wd, torch.tensor(w1, device="cuda"), torch.tensor(r0, device="cuda"), scale,
+                    tau, elems).cpu().numpy()
+    e = elems.cpu().numpy()
+    unit = 1.7 ** 3 * tau ** 2 / h
+    tref = ((w1 - w - tau * r0)[e].reshape(len(e), -1)) * (sign[e] / unit)[:, None]
+    assert np.abs(t - tref).max() <= 1e-6 * np.abs(tref).max()
+
+
+def test_forward_and_gradient_vs_oracle(env):
+    dg, S, mesh, sur = env
+    say("case surrogate forward/gradient")
+    p = mlp.init_params(5).astype(np.float32)
+    sur.load(p)
+    rng = np.random.default_rng(6)
+    x = rng.normal(size=(300, 80)).astype(np.float32)
+    t = rng.normal(size=(300, 20)).astype(np.float32) * 0.3
+    xd, td = torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda")
+    y = sur.forward(xd).cpu().numpy()
+    yref = mlp.forward(p.astype(np.float64), x.astype(np.float64))
+    e = rel(y, yref)
+    say("   forward rel %.3e" % e)
+    assert e < 3e-2
+    loss, g = sur.grad(xd, td)
+    lref, gref = mlp.loss_and_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    g = g.cpu().numpy().astype(np.float64)
+    cos = float(g @ gref / np.linalg.norm(g) / np.linalg.norm(gref))
+    eg = rel(g, gref)
+    say("   loss %.5f vs %.5f  grad rel %.3e  cos %.6f" % (loss.item(), lref, eg, cos))
+    assert abs(loss.item() - lref) < 3e-2 * lref
+    assert eg < 3e-2 and cos > 0.999
+
+
+def test_adam_step_matches_oracle_update(env):
+    dg, S, mesh, sur = env
+    say("case surrogate adam")
+    p = mlp.init_params(7).astype(np.float32)
+    sur.load(p)
+    rng = np.random.default_rng(8)
+    x = torch.tensor(rng.normal(size=(128, 80)), dtype=torch.float32, device="cuda")
+    t = torch.tensor(rng.normal(size=(128, 20)), dtype=torch.float32, device="cuda")
+    _, g = sur.grad(x, t)
+    g = g.cpu().numpy().astype(np.float64)
+    sur.train_step(x, t, 1e-3)
+    opt = mlp.Adam(p.size)
+    ref = opt.step(p.astype(np.float64), g, 1e-3)
+    got = sur.save().astype(np.float64)
+    assert np.abs(got - ref).max() < 1e-6
+
+
+def test_training_reduces_loss(env):
+    dg, S, mesh, sur = env
+    say("case surrogate training")
+    sur.load(mlp.init_params(9).astype(np.float32))
+    rng = np.random.default_rng(10)
+    A = rng.normal(size=(80, 20)) * 0.1
+    X = torch.tensor(rng.normal(size=(8192, 80)), dtype=torch.float32, device="cuda")
+    T = X @ torch.tensor(A, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    first = None
+    for it in range(300):
+        idx = torch.randint(0, 8192, (512,), device="cuda")
+        sur.train_step(X[idx].contiguous(), T[idx].contiguous(), 1e-3, loss)
+        if first is None:
+            first = loss.item()
+    say("   loss %.4f -> %.4f" % (first, loss.item()))
+    assert loss.item() < 0.1 * first
+
+
+def test_macro_step_fallback_paths(env):
+    dg, S, mesh, sur = env
+    say("case surrogate fallback")
+    sur.load(mlp.init_params(11).astype(np.float32))
+    w = torch.tensor(S.initial_state(mesh, 4), device="cuda")
+    dt = 0.1 / 16 / 9
+    ref = w.clone()
+    mesh.rk_substeps(ref, dt, 8)
+    # tol = 0 forces the fallback: the result is the plain substeps, bit for bit
+    ws = w.clone()
+    acc, rho = sur.macro_step(ws, dt, 0.0)
+    assert not acc and rho > 0 and torch.equal(ws, ref)
+    # non-finite parameters make a non-finite defect, which is rejected
+    p = mlp.init_params(11).astype(np.float32)
+    p[100] = np.nan
+    sur.load(p)
+    ws = w.clone()
+    acc, rho = sur.macro_step(ws, dt, 1e30)
+    assert not acc and not np.isfinite(rho) and torch.equal(ws, ref)
+    # an accepted candidate is w + tau r(w) + sigma (s^3 tau^2 / h) y exactly
+    sur.load(mlp.init_params(11).astype(np.float32))
+    ws = w.clone()
+    acc, rho = sur.macro_step(ws, dt, np.inf)
+    assert acc and np.isfinite(rho)
+    scale = mesh.reduce("maxvel", w)
+    x = sur.features(w, scale)
+    y = sur.forward(x)
+    X = mesh.vertices()
+    sign = torch.tensor(np.where(X[:, 1, 0] - X[:, 0, 0] < 0, -1.0, 1.0), device="cuda")
+    tau, h = 8 * dt, mesh.info["h_min"]
+    unit = scale[0] ** 3 * tau ** 2 / h
+    cand = w + tau * mesh.apply(w) + (sign * unit)[:, None, None] * y.double().view(w.shape)
+    assert torch.allclose(ws, cand, rtol=0, atol=1e-12)
