@@ -82,32 +82,34 @@ __device__ __forceinline__ s4 load4(const uint16_t* p, int64_t row, int64_t rs, 
 
 template <int EPI>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+  // wave tile 32 (M) x 64 (N): 2 x 4 MFMA tiles; workgroup 4 waves stacked along N (32 x 256)
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g4 = lane >> 4, c = lane & 15;
-  const int m0 = blockIdx.y * 64 + 32 * (w >> 1);
-  const int n0 = blockIdx.x * 64 + 32 * (w & 1);
-  f4 acc[2][2];
+  const int m0 = blockIdx.y * 32;
+  const int n0 = blockIdx.x * 256 + 64 * w;
+  if (n0 >= g.N) return;  // wave-uniform: no matrix instruction below runs partially
+  f4 acc[2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0, 0, 0, 0};
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0, 0, 0, 0};
   for (int k0 = 0; k0 < g.K; k0 += 16) {
     const int kk = k0 + 4 * g4;
-    s4 a[2], b[2];
+    s4 a[2], b[4];
 #pragma unroll
     for (int i = 0; i < 2; ++i) a[i] = load4(g.A, m0 + 16 * i + c, g.am, kk, g.ak, g.M, g.K);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) b[j] = load4(g.B, n0 + 16 * j + c, g.bn, kk, g.bk, g.N, g.K);
+    for (int j = 0; j < 4; ++j) b[j] = load4(g.B, n0 + 16 * j + c, g.bn, kk, g.bk, g.N, g.K);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 4; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + 16 * i + 4 * g4 + r, n = n0 + 16 * j + c;
@@ -131,7 +133,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
 
 template <int EPI>
 hipError_t gemm(const GemmArgs& g, hipStream_t s) {
-  const dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+  const dim3 grid((g.N + 255) / 256, (g.M + 31) / 32);
   hipLaunchKernelGGL(gemm_kernel<EPI>, grid, dim3(256), 0, s, g);
   return hipGetLastError();
 }
@@ -251,24 +253,20 @@ __global__ void update_kernel(int64_t E, int per, const float* sigma, const doub
   wt[i] = w[i] + tau * r0[i] + (double)sigma[T] * (s * s * s * tau * tau / h) * (double)y[i];
 }
 
-// trapezoid defect of the macro-step: num = sum |J| |wt - w - h/2 (r0 + r1)|^2,
-// den = sum |J| |wt - w|^2, per block
+// trapezoid defect of the macro-step: num = sum |J| |wt - w - tau/2 (r0 + r1)|^2,
+// den = sum |J| |wt - w|^2; one value per thread (coalesced), partial sums per block
 __global__ void __launch_bounds__(256)
 defect_kernel(int64_t E, int per, double half_T, const double* absdet, const double* w,
               const double* wt, const double* r0, const double* r1, double* partial) {
   __shared__ double sh[256][2];
-  const int64_t T = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double a = 0, b = 0;
-  if (T < E) {
-    for (int j = 0; j < per; ++j) {
-      const int64_t i = T * per + j;
-      const double d = wt[i] - w[i];
-      const double e = d - half_T * (r0[i] + r1[i]);
-      a = fma(e, e, a);
-      b = fma(d, d, b);
-    }
-    a *= absdet[T];
-    b *= absdet[T];
+  if (i < E * per) {
+    const double J = absdet[i / per];
+    const double d = wt[i] - w[i];
+    const double e = d - half_T * (r0[i] + r1[i]);
+    a = J * e * e;
+    b = J * d * d;
   }
   sh[threadIdx.x][0] = a;
   sh[threadIdx.x][1] = b;
@@ -493,7 +491,7 @@ dg_status dg_surrogate_create(const dg_mesh* m, int M, dg_surrogate** out) {
     HIP_TRY(hipMemcpy(s->nbr, m->h.nbr.data(), m->h.nbr.size() * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMalloc((void**)&s->scale, 4 * 8));
     HIP_TRY(hipMalloc((void**)&s->rho, 8));
-    HIP_TRY(hipMalloc((void**)&s->dpart, (nblk(s->E) + 1) * 2 * 8));
+    HIP_TRY(hipMalloc((void**)&s->dpart, (nblk(s->E * s->dim * s->np) + 1) * 2 * 8));
     HIP_TRY(hipMalloc((void**)&s->mwork, 3 * (size_t)s->E * s->dim * s->np * 8 + 64));
     return DG_OK;
   };
@@ -633,10 +631,11 @@ dg_status dg_macro_step(const dg_mesh* m, dg_surrogate* s, double* w, double dt,
   HIP_TRY(hipGetLastError());
   // a-posteriori check: trapezoid defect over the macro interval
   if ((st = dg_convection_apply(m, DG_FP64, wt, nullptr, r1, stream)) != DG_OK) return st;
-  hipLaunchKernelGGL(defect_kernel, dim3(nblk(E)), dim3(256), 0, hs, E, per, 0.5 * s->M * dt,
-                     m->d_absdet, w, wt, r0, r1, s->dpart);
+  hipLaunchKernelGGL(defect_kernel, dim3(nblk(E * per)), dim3(256), 0, hs, E, per,
+                     0.5 * s->M * dt, m->d_absdet, w, wt, r0, r1, s->dpart);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(defect_final_kernel, dim3(1), dim3(256), 0, hs, nblk(E), s->dpart, s->rho);
+  hipLaunchKernelGGL(defect_final_kernel, dim3(1), dim3(256), 0, hs, nblk(E * per), s->dpart,
+                     s->rho);
   HIP_TRY(hipGetLastError());
   double rho = 0;
   HIP_TRY(hipMemcpyAsync(&rho, s->rho, 8, hipMemcpyDeviceToHost, hs));

@@ -39,31 +39,49 @@ def init_params(seed, n_params):
     return p
 
 
-def generate(mesh, sur, seeds, n_macro, per_snapshot, M=8, k=3, device="cuda"):
+def initial_states(mesh, seeds, workers=8):
+    """Initial states of several seeds, evaluated on host threads (NumPy releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    x = mesh.project_points(4)
+    f = lambda s: mesh.project(synth.FourierField(2, seed=s)(x), 4)
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(f, seeds))
+
+
+def generate(mesh, sur, seeds, n_macro, per_snapshot, M=8, k=3, device="cuda", chunk=64):
     """Samples (x, t) from trajectories of the plain method: for each seed, n_macro macro
     intervals of M substeps; per interval `per_snapshot` random elements."""
     import torch
     h = 1.0 / round(np.sqrt(mesh.E / 2))
     xs, ts = [], []
     gen = torch.Generator(device=device)
-    for seed in seeds:
-        gen.manual_seed(int(seed))
-        w = torch.tensor(initial_state(mesh, seed), device=device)
-        s0 = float(mesh.reduce("maxvel", w)[0].item())
-        dt = 0.1 * h / (k * k * s0)
-        for _ in range(n_macro):
-            scale = mesh.reduce("maxvel", w)
-            elems = torch.randint(0, mesh.E, (per_snapshot,), generator=gen, device=device,
-                                  dtype=torch.int32)
-            x = sur.features(w, scale, elems)
-            r0 = mesh.apply(w)
-            w1 = w.clone()
-            mesh.rk_substeps(w1, dt, M)
-            t = sur.targets(w, w1, r0, scale, M * dt, elems)
-            xs.append(x)
-            ts.append(t)
-            w = w1
+    seeds = list(seeds)
+    for c0 in range(0, len(seeds), chunk):
+        batch = seeds[c0:c0 + chunk]
+        for seed, w_host in zip(batch, initial_states(mesh, batch)):
+            _trajectory(mesh, sur, seed, w_host, n_macro, per_snapshot, M, k, h, gen, xs, ts,
+                        device)
     return torch.cat(xs), torch.cat(ts)
+
+
+def _trajectory(mesh, sur, seed, w_host, n_macro, per_snapshot, M, k, h, gen, xs, ts, device):
+    """One trajectory of the plain method from w_host; appends the samples to xs, ts."""
+    import torch
+    gen.manual_seed(int(seed))
+    w = torch.tensor(w_host, device=device)
+    s0 = float(mesh.reduce("maxvel", w)[0].item())
+    dt = 0.1 * h / (k * k * s0)
+    for _ in range(n_macro):
+        scale = mesh.reduce("maxvel", w)
+        elems = torch.randint(0, mesh.E, (per_snapshot,), generator=gen, device=device,
+                              dtype=torch.int32)
+        x = sur.features(w, scale, elems)
+        r0 = mesh.apply(w)
+        w1 = w.clone()
+        mesh.rk_substeps(w1, dt, M)
+        xs.append(x)
+        ts.append(sur.targets(w, w1, r0, scale, M * dt, elems))
+        w = w1
 
 
 def train(sur, X, T, epochs, batch=4096, lr0=1e-3, lr1=1e-5, seed=0, log=None):
