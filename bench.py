@@ -23,6 +23,38 @@ PEAK_FP64 = 78.6e12  # MI355X FP64 vector (= FP64 matrix) peak, flop/s
 PEAK_FP32 = 157.3e12
 PEAK_HBM = 8.0e12
 
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs (FETCH_SIZE x2.00,
+# WRITE_SIZE x1.00: the factors a plain 512 MiB device copy gives), mean over the launches of
+# SSP-RK3 substeps; keyed by (config, precision, kernel) with the SHA-256 of the kernel sources
+# the counters were taken on.  Reported as null once those sources change.
+TRAFFIC_SOURCES = ("paper_1508_04245_amd/csrc/conv_kernels.hpp",
+                   "paper_1508_04245_amd/csrc/mfma_kernels.hpp",
+                   "paper_1508_04245_amd/csrc/dgconv.hip")
+MEASURED_TRAFFIC = {
+    ("c2", "fp64", "valu"): (128.3e6, "83db17d191f4380b"),
+}
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for p in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_label(cfg, precision, fp64_kernel):
+    """Which operator kernel the library runs (its default: matrix cores for FP64 when the
+    element has >= 20 basis functions per component)."""
+    NP, _, _ = shape_counts(cfg["dim"], cfg["k"])
+    if precision == "fp64":
+        kind = fp64_kernel or ("mfma" if NP >= 20 else "valu")
+    else:
+        kind = "valu" if precision == "fp32" else "mfma"
+    name = "conv_kernel" if kind == "valu" else "mconv_kernel"
+    return kind, "%s<%d,%d,%s,self>" % (name, cfg["dim"], cfg["k"], precision)
+
 CONFIGS = {
     "c1": dict(dim=2, n=16, k=2, field="tg"),
     "c2": dict(dim=2, n=256, k=4, field="tg"),
@@ -163,6 +195,9 @@ def main():
     byts = alg_bytes_per_elem(cfg["dim"], cfg["k"], esz=8 if ty == torch.float64 else 4) * E
     peak = PEAK_FP64 if ty == torch.float64 else PEAK_FP32
     finite = torch.isfinite(w).all().item()
+    kind, label = kernel_label(cfg, args.precision, args.fp64_kernel)
+    tr = MEASURED_TRAFFIC.get((args.config, args.precision, kind))
+    traffic = tr[0] if tr and not args.n and tr[1] == kernel_sources_hash() else None
     out = {
         "metric": "DG convection DOF-updates/s (SSP-RK3 substeps), FP64",
         "value": value,
@@ -184,8 +219,8 @@ def main():
                    % (cfg["n"], E, cfg["k"], dt),
                    "config": args.config, "n_dof": ndof, "precision": args.precision},
         "roofline": {"bound": "alu", "achieved": flops / per_launch / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": flops / per_launch / peak, "traffic": None,
-                     "kernel": "conv_kernel<%d,%d,%s,self>" % (cfg["dim"], cfg["k"], args.precision),
+                     "unit": "TFLOP/s", "frac": flops / per_launch / peak, "traffic": traffic,
+                     "traffic_unit": "B/launch", "alg_bytes": byts, "kernel": label,
                      "launch_us": per_launch * 1e6,
                      "hbm_equiv_GBps": byts / per_launch / 1e9},
         "wall_s": wall,

@@ -136,3 +136,20 @@ def test_error_paths():
     with pytest.raises(dg.DGError) as e:
         dg.Mesh.from_arrays(2, 1, xyz, bad, np.ones(2))
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("name", ["dubiner_2d_k3.txt", "dubiner_3d_k2.txt"])
+def test_basis_matches_golden_exact_values(name):
+    """Stored exact-rational Gram-Schmidt basis values (tests/golden/make_golden.py)."""
+    from fractions import Fraction
+    lines = open(os.path.join(ROOT, "tests", "golden", name)).read().split("\n")
+    dim, k = map(int, lines[0].split())
+    for ln in lines[1:]:
+        if not ln.strip():
+            continue
+        tok = ln.split()
+        pt = np.array([[float(Fraction(t)) for t in tok[:dim]]])
+        ref = np.array([float(t) for t in tok[dim:]])
+        v, _ = dg.eval_basis(dim, k, pt)
+        assert np.abs(v[0] - ref).max() < 1e-14 * max(1.0, np.abs(ref).max())
+        assert np.abs(R.eval_basis(dim, k, pt)[0] - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
