@@ -5,11 +5,12 @@
 // (4 wavefronts) covers one block of 256 consecutive elements, so all writes to a cache line
 // of the state come from one CU, and hardware blocks are remapped so that each XCD (blocks
 // are dealt round-robin over the 8 XCDs) works on one contiguous range of the mesh and finds
-// most neighbour states in its own L2.  Tables are staged in LDS when they fit (64 KiB) and
-// read with wave-uniform addresses (broadcast reads, returned in order so the compiler can
-// pipeline them); larger tables are read through constant-address-space pointers (scalar
-// loads into SGPRs).  Each multiply-add of a basis contraction is one VALU FMA.  The
-// per-element state, the neighbour states and the accumulators stay in VGPRs.
+// most neighbour states in its own L2.  Each reference table is read either from LDS (staged
+// per workgroup when the tables fit in 64 KiB; wave-uniform broadcast reads) or through a
+// constant-address-space pointer (scalar loads into SGPRs); the split is chosen per element
+// type so that neither the LDS return path nor the scalar loads' latency dominates.  Each
+// multiply-add of a basis contraction is one VALU FMA.  The per-element state, the neighbour
+// states and the accumulators stay in VGPRs.
 //
 // Per element and application (Sec. 2.3 upwind form, Sec. 2.4 discrete operator, inverse of
 // the diagonal mass matrix folded in):
@@ -74,22 +75,45 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
   return x * q + (x < r ? x : r) + j;
 }
 
-template <bool LDS, typename T>
-struct Tab {
+// Source of each reference table: bit t of the mask set = table t is read through a
+// constant-address-space pointer (wave-uniform scalar loads into SGPRs, one copy per wave),
+// clear = staged in LDS and read with broadcast addresses (the LDS returns the value to every
+// lane, so those reads cost LDS bandwidth per lane).  Splitting the tables between the two
+// paths keeps the LDS return bandwidth below the FP64 FMA rate.
+enum { TB_BV = 0, TB_DV = 1, TB_TRO = 2, TB_TRN = 3, TB_LF = 4 };
+constexpr int SM_ALL = 31;
+
+template <int SM, typename T>
+struct Tabs {
   typedef const T __attribute__((address_space(4)))* cptr;
   const T* l;
   cptr c;
-  __device__ __forceinline__ T operator[](int i) const {
-    if constexpr (LDS) return l[i];
-    else return c[i];
+  template <int ID>
+  __device__ __forceinline__ T get(int i) const {
+    if constexpr ((SM >> ID) & 1) return c[i];
+    else return l[i];
   }
 };
+
+// stage the LDS-sourced tables (contiguous ranges of the table block) into LDS
+template <int D, int K, int SM, typename T>
+__device__ __forceinline__ void stage_tables(T* stab, const T* tab) {
+  using S = Shape<D, K>;
+  constexpr int beg[5] = {S::OFF_BV, S::OFF_DV, S::OFF_TR, S::OFF_TR, S::OFF_LF};
+  constexpr int end[5] = {S::OFF_DV, S::OFF_TR, S::OFF_LF, S::OFF_LF, S::TOTAL};
+#pragma unroll
+  for (int t = 0; t < 5; ++t) {
+    if (t == TB_TRN && !((SM >> TB_TRO) & 1)) continue;  // same range as the own traces
+    if ((SM >> t) & 1) continue;
+    for (int i = beg[t] + (int)threadIdx.x; i < end[t]; i += 256) stab[i] = tab[i];
+  }
+}
 
 // occupancy target: two waves per SIMD (<= 256 VGPR+AGPR per lane) where the state fits
 template <int D, int K, typename T>
 constexpr int min_waves() { return Shape<D, K>::NP * D * sizeof(T) <= 15 * 2 * 8 ? 2 : 1; }
 
-template <int D, int K, typename T, bool SELF, bool LDS>
+template <int D, int K, typename T, bool SELF, int SM>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvArgs<T> A) {
   using S = Shape<D, K>;
@@ -98,14 +122,15 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
   const int lane = threadIdx.x & 63;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int tile = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
-  Tab<LDS, T> tab;
-  if constexpr (LDS) {
-    __shared__ T stab[LDS ? S::TOTAL : 1];
-    for (int i = threadIdx.x; i < S::TOTAL; i += 256) stab[i] = A.tab[i];
+  Tabs<SM, T> tab;
+  tab.c = (typename Tabs<SM, T>::cptr)A.tab;
+  if constexpr (SM != SM_ALL) {
+    __shared__ T stab[S::TOTAL];
+    stage_tables<D, K, SM>(stab, A.tab);
     __syncthreads();
     tab.l = stab;
   } else {
-    tab.c = (typename Tab<LDS, T>::cptr)A.tab;
+    tab.l = A.tab;
   }
   const int type = __builtin_amdgcn_readfirstlane(A.tile_type[tile]);
   if (type < 0) return;  // empty tile padding a block
@@ -148,7 +173,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
     for (int i = 0; i < D; ++i) wq[i] = T(0);
 #pragma unroll
     for (int m = 0; m < NP; ++m) {
-      const T bm = tab[bq + m];
+      const T bm = tab.template get<TB_BV>(bq + m);
 #pragma unroll
       for (int i = 0; i < D; ++i) wq[i] = fma(bm, c[i][m], wq[i]);
     }
@@ -160,7 +185,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
       for (int i = 0; i < D; ++i) uq[i] = T(0);
 #pragma unroll
       for (int m = 0; m < NP; ++m) {
-        const T bm = tab[bq + m];
+        const T bm = tab.template get<TB_BV>(bq + m);
 #pragma unroll
         for (int i = 0; i < D; ++i) uq[i] = fma(bm, uc[i][m], uq[i]);
       }
@@ -176,7 +201,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
     for (int m = 0; m < NP; ++m) {
       T P = T(0);
 #pragma unroll
-      for (int a = 0; a < D; ++a) P = fma(uh[a], tab[dq + m * D + a], P);
+      for (int a = 0; a < D; ++a) P = fma(uh[a], tab.template get<TB_DV>(dq + m * D + a), P);
 #pragma unroll
       for (int i = 0; i < D; ++i) R[i][m] = fma(wq[i], P, R[i][m]);
     }
@@ -222,7 +247,8 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
       for (int i = 0; i < D; ++i) { wm[i] = T(0); wp[i] = T(0); }
 #pragma unroll
       for (int m = 0; m < NP; ++m) {
-        const T to = tab[tro + q * NP + m], tn = tab[trn + q * NP + m];
+        const T to = tab.template get<TB_TRO>(tro + q * NP + m);
+        const T tn = tab.template get<TB_TRN>(trn + q * NP + m);
 #pragma unroll
         for (int i = 0; i < D; ++i) {
           wm[i] = fma(to, c[i][m], wm[i]);
@@ -237,7 +263,8 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
         for (int i = 0; i < D; ++i) { um[i] = T(0); up[i] = T(0); }
 #pragma unroll
         for (int m = 0; m < NP; ++m) {
-          const T to = tab[tro + q * NP + m], tn = tab[trn + q * NP + m];
+          const T to = tab.template get<TB_TRO>(tro + q * NP + m);
+        const T tn = tab.template get<TB_TRN>(trn + q * NP + m);
 #pragma unroll
           for (int i = 0; i < D; ++i) {
             um[i] = fma(to, uc[i][m], um[i]);
@@ -256,7 +283,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
       for (int i = 0; i < D; ++i) F[i] = hb * (wm[i] + wp[i]) + ha * (wm[i] - wp[i]);
 #pragma unroll
       for (int m = 0; m < NP; ++m) {
-        const T l = tab[lfo + q * NP + m];
+        const T l = tab.template get<TB_LF>(lfo + q * NP + m);
 #pragma unroll
         for (int i = 0; i < D; ++i) R[i][m] = fma(-l, F[i], R[i][m]);
       }

@@ -148,18 +148,48 @@ hipError_t launch_maxvel(const dg_mesh* m, const double* a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// default table sources of the VALU kernel (bit t of the mask: table t read through scalar
+// loads, else from LDS; t = basis values, gradients, own traces, neighbour traces, lifts).
+// Tables too large for LDS all come through scalar loads.  For 2D P4 the basis values, own
+// traces and lifts through scalar loads halve the LDS reads per wave (measured on MI355X,
+// 2D 256x256x2 P4: 51.5 us per launch against 57.6 us with every table in LDS); smaller
+// elements keep every table in LDS.
+template <int D, int K, typename T>
+constexpr int default_tab_src() {
+  if (!dgk::tables_in_lds<D, K, T>()) return dgk::SM_ALL;
+  if (D == 2 && K == 4 && sizeof(T) == 8) return 21;
+  return 0;
+}
+
+template <int D, int K, typename T, bool SELF, int SM>
+void launch_conv_sm(const dgk::ConvArgs<T>& a, dim3 grid, hipStream_t s) {
+  hipLaunchKernelGGL((dgk::conv_kernel<D, K, T, SELF, SM>), grid, dim3(256), 0, s, a);
+}
+
 template <int D, int K, typename T, bool SELF>
 hipError_t launch_conv_dk(const dg_mesh* m, const dgk::ConvArgs<T>& a, hipStream_t s) {
-  constexpr bool kLdsOk = dgk::tables_in_lds<D, K, T>();
+  constexpr int kDef = default_tab_src<D, K, T>();
   // the kernel's compile-time table layout must match the host tables it reads
   if ((size_t)dgk::Shape<D, K>::TOTAL != m->t.total || dgk::Shape<D, K>::NP != m->h.np)
     return hipErrorInvalidValue;
   if ((int64_t)m->h.elem_list.size() != (int64_t)m->h.ntiles * 64) return hipErrorInvalidValue;
-  const dim3 grid((m->h.ntiles + 3) / 4), block(256);
-  if (kLdsOk && m->tables_lds)
-    hipLaunchKernelGGL((dgk::conv_kernel<D, K, T, SELF, kLdsOk>), grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL((dgk::conv_kernel<D, K, T, SELF, false>), grid, block, 0, s, a);
+  const dim3 grid((m->h.ntiles + 3) / 4);
+  // DGCONV_TABLES may pick another split for the FP64 self kernel: every table in LDS (0),
+  // every table through scalar loads (31), or the 2D P4 default (21)
+  const int src = m->tab_src < 0 || !dgk::tables_in_lds<D, K, T>() ? kDef : m->tab_src;
+  if constexpr (dgk::tables_in_lds<D, K, T>() && SELF && sizeof(T) == 8) {
+    if (src != kDef) {
+      switch (src) {
+        case 0: launch_conv_sm<D, K, T, SELF, 0>(a, grid, s); return hipGetLastError();
+        case 21: launch_conv_sm<D, K, T, SELF, 21>(a, grid, s); return hipGetLastError();
+        case dgk::SM_ALL:
+          launch_conv_sm<D, K, T, SELF, dgk::SM_ALL>(a, grid, s);
+          return hipGetLastError();
+        default: return hipErrorInvalidValue;
+      }
+    }
+  }
+  launch_conv_sm<D, K, T, SELF, kDef>(a, grid, s);
   return hipGetLastError();
 }
 
@@ -505,10 +535,10 @@ dg_status dg_mesh_create(int dim, int k, int64_t n_vert, const double* xyz, int6
   dgmesh::build_tables(dim, k, m->t);
   m->n_partial = (int)((n_elem + kRedBlock - 1) / kRedBlock);
   {
-    // LDS tables by default (measured faster on c2: 57 us vs 88 us per launch);
-    // DGCONV_TABLES=smem reads them through scalar loads instead
+    // VALU kernel table sources: DGCONV_TABLES = lds | smem | <mask> (bit t: table t through
+    // scalar loads; t = basis values, gradients, own traces, neighbour traces, lifts)
     const char* tm = std::getenv("DGCONV_TABLES");
-    m->tables_lds = !(tm && std::string(tm) == "smem");
+    if (tm) m->tab_src = std::string(tm) == "lds" ? 0 : std::string(tm) == "smem" ? 31 : std::atoi(tm);
     // FP64 kernel: matrix cores for large elements (n_basis >= 20: measured 2x faster on 3D
     // P3), the VALU kernel otherwise (faster on 3D P2, equal on 2D P4);
     // DGCONV_FP64_KERNEL=valu|mfma overrides

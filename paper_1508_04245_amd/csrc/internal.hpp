@@ -42,7 +42,7 @@ struct dg_mesh {
   double* d_partial = nullptr;  // reduction partials
   int n_partial = 0;
   bool on_device = false;
-  bool tables_lds = false;  // stage reference tables in LDS (where they fit) or read via SGPRs
+  int tab_src = -1;  // VALU kernel table sources (bit t: table t via scalar loads); -1: default
   bool fp64_mfma = false;   // FP64 operator on the matrix cores instead of the VALU kernel
   // matrix-core path: 16-wide tiles and fragment tables per contraction engine
   int* d_elem_list16 = nullptr;
