@@ -138,6 +138,64 @@ def cpu_baseline(cfg, budget_s=30.0):
                       % (n, wall, len(os.sched_getaffinity(0)))}
 
 
+STUDY_STEPS = {"c1": 100, "c2": 200, "c3": 40, "c4": 20, "c5": 200}
+
+
+def precision_study(dg, cfgs, tol=1e-6):
+    """Each precision variant against FP64 from the same initial state: final-state relative
+    L2 error after a fixed number of substeps, time per substep, and the speedup of the
+    cheapest variant within `tol` (one JSON line per configuration)."""
+    import torch
+    dev = torch.device("cuda", 0)
+    variants = [("fp64", None), ("fp64", "valu"), ("fp64", "mfma"), ("fp32", None),
+                ("f16x2", None), ("bf16x3", None)]
+    for name in cfgs:
+        cfg = CONFIGS[name]
+        steps = STUDY_STEPS[name]
+        rows = []
+        ref = None
+        w_host = None
+        for prec, kern in variants:
+            if kern:
+                os.environ["DGCONV_FP64_KERNEL"] = kern
+            else:
+                os.environ.pop("DGCONV_FP64_KERNEL", None)
+            if w_host is None:
+                m, w_host = make_state(dg, cfg)
+            else:
+                m = dg.Mesh.box(cfg["dim"], cfg["n"], cfg["k"])  # kernel choice is per mesh
+            w64 = torch.tensor(w_host, dtype=torch.float64, device=dev)
+            umax = float(m.reduce("maxvel", w64)[0].item())
+            dt = 0.1 / cfg["n"] / (max(cfg["k"], 1) ** 2 * umax)
+            ty = torch.float32 if prec == "fp32" else torch.float64
+            w = w64.to(ty)
+            work = torch.empty((2,) + tuple(w.shape), dtype=ty, device=dev)
+            m.rk_substeps(w.clone(), dt, 2, work=work, precision=prec)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            m.rk_substeps(w, dt, steps, work=work, precision=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / 1e3 / steps
+            wf = w.to(torch.float64)
+            if ref is None:
+                ref = wf.clone()
+            d = m.reduce("l2diff", wf, ref)
+            err = float(d[0].item() / d[1].item())
+            rows.append({"precision": prec, "kernel": kern or "default", "rel_l2_vs_fp64": err,
+                         "s_per_substep": t})
+            del m
+        os.environ.pop("DGCONV_FP64_KERNEL", None)
+        t64 = rows[0]["s_per_substep"]
+        for r in rows:
+            r["speedup_vs_fp64_default"] = t64 / r["s_per_substep"]
+        ok = [r for r in rows[1:] if r["rel_l2_vs_fp64"] <= tol]
+        best = max(ok, key=lambda r: r["speedup_vs_fp64_default"]) if ok else None
+        print(json.dumps({"config": name, "substeps": steps, "tol": tol, "variants": rows,
+                          "best_within_tol": best}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +208,9 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the mesh size (experiments)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
+    ap.add_argument("--precision-study", default=None, metavar="CFGS",
+                    help="comma-separated configs: final-state error and speedup of every "
+                         "precision variant against FP64 (one JSON line per config)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the multi-GPU sharding is a design in DESIGN.md,"
@@ -161,6 +222,9 @@ def main():
     import torch
     import paper_1508_04245_amd as dg
     dg.lib()
+    if args.precision_study:
+        precision_study(dg, args.precision_study.split(","))
+        return
     cfg = dict(CONFIGS[args.config])
     if args.n:
         cfg["n"] = args.n
@@ -195,6 +259,15 @@ def main():
     byts = alg_bytes_per_elem(cfg["dim"], cfg["k"], esz=8 if ty == torch.float64 else 4) * E
     peak = PEAK_FP64 if ty == torch.float64 else PEAK_FP32
     finite = torch.isfinite(w).all().item()
+    # single operator applications (mode r = L(w), no Runge-Kutta stage), same stream
+    r_out = torch.empty_like(w)
+    n_app = max(10, args.steps // 10)
+    ev0.record(stream)
+    for _ in range(n_app):
+        m.apply(w, out=r_out, precision=prec)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    apply_s = ev0.elapsed_time(ev1) / 1e3 / n_app
     kind, label = kernel_label(cfg, args.precision, args.fp64_kernel)
     tr = MEASURED_TRAFFIC.get((args.config, args.precision, kind))
     traffic = tr[0] if tr and not args.n and tr[1] == kernel_sources_hash() else None
@@ -223,6 +296,7 @@ def main():
                      "traffic_unit": "B/launch", "alg_bytes": byts, "kernel": label,
                      "launch_us": per_launch * 1e6,
                      "hbm_equiv_GBps": byts / per_launch / 1e9},
+        "dof_applies_per_s": ndof / apply_s,
         "wall_s": wall,
         "final_state_finite": bool(finite),
     }

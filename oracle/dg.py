@@ -134,6 +134,26 @@ class Space:
             w = w / 3.0 + 2.0 / 3.0 * (w2 + dt * self.apply(w2, u))
         return w
 
+    def ssprk3_extrap(self, w, dt, n, t0, ua, ta, ub, tb):
+        """n SSP-RK3 substeps of the propagation problem (Sec. 3.2, "The propagation
+        operator", eq. explproblem) with the convecting velocity extrapolated linearly in time
+        from two stored fields: u(s) = ua + (s - ta) / (tb - ta) (ub - ua).  Substep j starts
+        at s_j = t0 + j dt; the Shu-Osher stages evaluate the operator at s_j, s_j + dt and
+        s_j + dt / 2."""
+        ua = np.asarray(ua, dtype=np.float64)
+        dub = np.asarray(ub, dtype=np.float64) - ua
+
+        def u_at(s):
+            return ua + ((s - ta) / (tb - ta)) * dub
+
+        w = np.array(w, dtype=np.float64, copy=True)
+        for j in range(n):
+            s = t0 + j * dt
+            w1 = w + dt * self.apply(w, u_at(s))
+            w2 = 0.75 * w + 0.25 * (w1 + dt * self.apply(w1, u_at(s + dt)))
+            w = w / 3.0 + 2.0 / 3.0 * (w2 + dt * self.apply(w2, u_at(s + 0.5 * dt)))
+        return w
+
     # ---- projection and functionals ----------------------------------------------------
     def quad_points(self, n):
         """Physical points of a collapsed rule with n points per direction: [E, Q, d]."""

@@ -268,3 +268,54 @@ def test_convergence_order_shear_wave_3d():
 
 def test_cfl_dt():
     assert np.isclose(cfl_dt(1 / 16, 2, 1.0), 0.1 / 16 / 4)
+
+
+# ---------------------------------------------------------------- extrapolated velocity
+def test_extrapolated_stepper_with_equal_fields_is_the_frozen_stepper():
+    m = box_mesh(2, 3, jitter=0.1, seed=2)
+    sp = Space(m, 2)
+    w, u = rand_state(sp, 1), rand_state(sp, 2, 0.3)
+    a = sp.ssprk3(w, 0.003, 4, u)
+    b = sp.ssprk3_extrap(w, 0.003, 4, 0.7, u, 0.0, u, 1.0)
+    assert np.array_equal(a, b)
+
+
+def _const_velocity(sp, v):
+    U = np.zeros(sp.shape)
+    U[:, :, 0] = np.array(v) / R.eval_basis(sp.dim, 0, np.zeros((1, sp.dim)))[0, 0]
+    return U
+
+
+def test_extrapolated_stepper_is_third_order_in_time():
+    """A convecting velocity that changes strongly within the interval: the time error of
+    the substeps falls by 2^3 per halving of dt only if every stage sees the velocity at its
+    own time (stages at the substep start would leave first order)."""
+    m = box_mesh(2, 4)
+    sp = Space(m, 2)
+    x = sp.quad_points(8)
+    w0 = sp.project(synth.taylor_green_2d(x), 8)
+    ua, ub = _const_velocity(sp, (1.0, 0.5)), _const_velocity(sp, (-0.5, 1.0))
+    T = 0.05
+    run = lambda n: sp.ssprk3_extrap(w0, T / n, n, 0.0, ua, 0.0, ub, T)
+    ref = run(256)
+    errs = [sp.l2_norm(run(n) - ref) for n in (8, 16, 32)]
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates.min() > 2.7, rates
+
+
+def test_extrapolated_stepper_dissipates_energy_for_curl_fields():
+    """Exactly divergence-free, normal-continuous fields at both times stay so at every stage
+    (a linear combination), so each stage operator is dissipative (Sec. 2.3 stability) and
+    small SSP-RK3 substeps do not increase the energy."""
+    m = box_mesh(2, 4)
+    sp = Space(m, 3)
+    ua, ub = _p1_curl_velocity(sp, 6), _p1_curl_velocity(sp, 7)
+    w = rand_state(sp, 8)
+    e = [sp.energy(w)]
+    umax = max(sp.max_speed(ua), sp.max_speed(ub))
+    dt = cfl_dt(0.25, 3, umax)
+    for j in range(6):
+        w = sp.ssprk3_extrap(w, dt, 1, j * dt, ua, 0.0, ub, 6 * dt)
+        e.append(sp.energy(w))
+    assert all(b <= a * (1 + 1e-13) for a, b in zip(e[:-1], e[1:])), e
+    assert e[-1] < e[0]
