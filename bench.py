@@ -213,8 +213,9 @@ def main():
                          "precision variant against FP64 (one JSON line per config)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (the multi-GPU sharding is a design in DESIGN.md,"
-              " not built); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the path's sharding over several GPUs (element "
+              "slabs with one boundary exchange per stage) is designed, not built; use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.fp64_kernel:

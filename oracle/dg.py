@@ -14,7 +14,7 @@ propagation problem):
 with w^ the upwind value (the trace of w taken from the side the flow comes from) and M^V the
 DG mass matrix, diagonal for an L2-orthogonal basis (Sec. 2.3).
 
-Readings where the paper leaves the hot path open (each also listed in the design doc):
+Readings where the paper leaves the hot path open:
   * The paper's convecting velocity is H(div)-conforming, so u.n is single-valued.  For a
     discontinuous convecting field we use the facet-averaged normal velocity
     beta = 1/2 (u^- + u^+) . n^-, and w^ = w^- if beta > 0 else w^+ (at beta = 0 the flux is 0
@@ -153,6 +153,30 @@ class Space:
             w2 = 0.75 * w + 0.25 * (w1 + dt * self.apply(w1, u_at(s + dt)))
             w = w / 3.0 + 2.0 / 3.0 * (w2 + dt * self.apply(w2, u_at(s + 0.5 * dt)))
         return w
+
+    def richardson(self, g, u, tau, ds, rtol, max_it, v0=None):
+        """Pseudo-time iteration for the implicit convection problem with frozen convection
+        (Sec. 3.3, eq. implconv):  v + tau (M^V)^-1 C^V(u) v = g.  Explicit Euler steps of size
+        ds in pseudo time (eq. implconvit, read with the sign that makes the residual of
+        eq. implconv vanish at the fixed point):
+
+            res_i   = g - v_i + tau r(v_i),   r = -(M^V)^-1 C^V(u) v  (= self.apply)
+            v_{i+1} = v_i + ds res_i
+
+        from v_0 (default g), until ||res_i|| <= rtol ||res_0|| (L2 norm), at most max_it
+        updates.  Returns (v_n, n, [||res_0||, ..., ||res_{n'}||]) with n the number of updates
+        (v_n is the first iterate meeting the criterion, or v_max_it) and the residual norms of
+        the iterates v_0 .. v_n' that were evaluated."""
+        g = np.asarray(g, dtype=np.float64)
+        v = np.array(g if v0 is None else v0, dtype=np.float64, copy=True)
+        hist = []
+        for i in range(max_it):
+            res = g - v + tau * self.apply(v, u)
+            hist.append(self.l2_norm(res))
+            if hist[-1] <= rtol * hist[0]:
+                return v, i, hist
+            v = v + ds * res
+        return v, max_it, hist
 
     # ---- projection and functionals ----------------------------------------------------
     def quad_points(self, n):

@@ -319,3 +319,54 @@ def test_extrapolated_stepper_dissipates_energy_for_curl_fields():
         e.append(sp.energy(w))
     assert all(b <= a * (1 + 1e-13) for a, b in zip(e[:-1], e[1:])), e
     assert e[-1] < e[0]
+
+
+# ---------------------------------------------------------------- implicit convection solve
+@pytest.mark.parametrize("dim,N,k,jit,u", [(2, 3, 1, 0.1, (0.75, -0.5)),
+                                           (2, 2, 2, 0.0, (-0.5, 0.25)),
+                                           (3, 2, 1, 0.0, (1.0, 1.0 / 3.0, 1.0 / 7.0))])
+def test_richardson_solves_the_implicit_convection_problem(dim, N, k, jit, u):
+    """The fixed point of the pseudo-time iteration is the solution of
+    (I - tau L) v = g with L the operator matrix assembled exactly in rational arithmetic
+    (r = L w for constant u), solved here by a dense direct solve."""
+    m = box_mesh(dim, N, jitter=jit, seed=11)
+    sp = Space(m, k)
+    L = assemble_frozen_constant(m.X, m.period, k, u, m.nbr, m.nbr_facet, m.shift)
+    U = _const_velocity(sp, u)
+    g = rand_state(sp, 13)
+    h = 1.0 / N
+    tau = 0.5 * h  # tau |u| / h ~ 0.5: a stiff but not extreme implicit step
+    lam = np.linalg.eigvals(np.eye(L.shape[0]) - tau * L)
+    ds = 2.0 * np.min(lam.real / np.abs(lam) ** 2) * 0.9  # inside the Euler stability region
+    v, n, hist = sp.richardson(g, U, tau, ds, 1e-13, 20000)
+    assert n < 20000 and hist[-1] <= 1e-13 * hist[0]
+    A = np.eye(L.shape[0]) - tau * L
+    for i in range(dim):
+        ref = np.linalg.solve(A, g[:, i, :].ravel()).reshape(m.E, sp.np)
+        assert np.abs(v[:, i, :] - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_richardson_contracts_at_the_euler_rate():
+    """For the linear problem the residual obeys res_{i+1} = (I - ds (I - tau L)) res_i, so
+    the ratio of successive residual norms approaches the spectral radius of that matrix."""
+    m = box_mesh(2, 3)
+    sp = Space(m, 1)
+    u = (0.6, 0.3)
+    L = assemble_frozen_constant(m.X, m.period, 1, u, m.nbr, m.nbr_facet, m.shift)
+    A = np.eye(L.shape[0]) - 0.1 * L
+    ds = 0.5
+    rho = np.abs(np.linalg.eigvals(np.eye(L.shape[0]) - ds * A)).max()
+    v, n, hist = sp.richardson(rand_state(sp, 3), _const_velocity(sp, u), 0.1, ds, 1e-12, 5000)
+    ratios = np.array(hist[1:]) / np.array(hist[:-1])
+    assert ratios.max() <= rho * (1 + 1e-9) + 1e-12
+    assert abs(ratios[-5:].mean() - rho) < 0.05
+
+
+def test_richardson_stops_at_once_on_a_zero_residual():
+    """g = 0 from v_0 = 0: the initial residual is exactly zero and no update is made."""
+    m = box_mesh(2, 2)
+    sp = Space(m, 2)
+    U = rand_state(sp, 1)
+    g = np.zeros(sp.shape)
+    out, n, hist = sp.richardson(g, U, 0.3, 0.5, 1e-8, 100)
+    assert n == 0 and hist == [0.0] and not out.any()
