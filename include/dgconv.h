@@ -120,6 +120,39 @@ dg_status dg_convection_apply(const dg_mesh* mesh, dg_precision prec, const void
 dg_status dg_rk_substeps(const dg_mesh* mesh, dg_precision prec, void* w, double dt, int n,
                          const void* u, void* work, void* stream);
 
+/* Pseudo-time (Richardson) iteration for the implicit convection problem of Sec. 3.3 with
+ * frozen convection (eq. implconv):  v + tau (M^V)^-1 C^V(u) v = g.  Explicit Euler steps of
+ * size ds in pseudo time (eq. implconvit, with the sign for which the fixed point solves
+ * eq. implconv):
+ *   res_i = g - v_i + tau r(v_i),  r(v) = -(M^V)^-1 C^V(u) v;   v_{i+1} = v_i + ds res_i,
+ * stopping at the first i with ||res_i|| <= rtol ||res_0|| (L2 norm over the mesh), after at
+ * most max_it updates.  Each update is one fused operator launch that also sums |det J| res^2
+ * per tile; the criterion is evaluated on the device and the host checks it every few
+ * iterations, so the iterates stop exactly at the first one that meets it.
+ * v: dev FP64 state, the initial guess on entry (e.g. a copy of g), on exit the first iterate
+ * meeting the criterion or v_max_it.  g, u: dev FP64 states (u is required: the convection is
+ * frozen).  work: dev, at least one state, or NULL for the mesh-owned buffer (then calls on
+ * one mesh must be serialised).  No argument may alias another.  prec: DG_FP64 or a mixed
+ * precision (operator contractions only; the iterate, residual and norms stay FP64); DG_FP32
+ * gives DG_EUNSUPPORTED.  tau finite, ds > 0, rtol >= 0, max_it >= 0.  iters_out (host, may
+ * be NULL): the number n of updates (the returned iterate is v_n); res_out (host double[2],
+ * may be NULL): ||res_0|| and the last residual norm evaluated.  Synchronises the stream. */
+dg_status dg_richardson(const dg_mesh* mesh, dg_precision prec, double* v, const double* g,
+                        const double* u, double tau, double ds, double rtol, int max_it,
+                        double* work, void* stream, int* iters_out, double* res_out);
+
+/* The propagation problem of Sec. 3.2 ("The propagation operator", eq. explproblem): n
+ * SSP-RK3 substeps as dg_rk_substeps, with the convecting velocity extrapolated linearly in
+ * time from two stored fields,
+ *   u(s) = ua + (s - ta) / (tb - ta) (ub - ua),
+ * evaluated at each stage's own time: substep j starts at s_j = t0 + j dt and its stages use
+ * u(s_j), u(s_j + dt), u(s_j + dt/2).  ua, ub: dev states (same element type as w), neither
+ * aliasing w; t0, ta, tb finite, tb != ta (ta, tb are the times of the stored fields, e.g. the
+ * two previous steps for extrapolation).  Other arguments and errors as dg_rk_substeps. */
+dg_status dg_rk_substeps_extrap(const dg_mesh* mesh, dg_precision prec, void* w, double dt,
+                                int n, double t0, const void* ua, double ta, const void* ub,
+                                double tb, void* work, void* stream);
+
 /* Reductions of FP64 states into out_dev (dev, doubles), deterministic:
  *   DG_RED_MAXVEL   out[0] = max over the volume quadrature points of |a(x)|
  *   DG_RED_ENERGY   out[0] = 1/2 int |a|^2 dx

@@ -55,6 +55,8 @@ def lib():
         "dg_project": [P, I, P, P],
         "dg_convection_apply": [P, I, P, P, P, P],
         "dg_rk_substeps": [P, I, P, D, I, P, P, P],
+        "dg_rk_substeps_extrap": [P, I, P, D, I, D, P, D, P, D, P, P],
+        "dg_richardson": [P, I, P, P, P, D, D, D, I, P, P, P, P],
         "dg_reduce": [P, I, P, P, P, P],
         "dg_eval_basis": [I, I, I64, P, P, P],
         "dg_surrogate_n_params": [P],
@@ -194,6 +196,32 @@ class Mesh:
                                     None if u is None else _dev(u, ty),
                                     None if work is None else _dev(work, ty), _stream(stream)))
         return w
+
+    def rk_substeps_extrap(self, w, dt, n, t0, ua, ta, ub, tb, work=None, precision="fp64",
+                           stream=None):
+        """n SSP-RK3 substeps in place on w with u(s) = ua + (s-ta)/(tb-ta) (ub-ua)."""
+        import torch
+        ty = torch.float32 if precision == "fp32" else torch.float64
+        _check(lib().dg_rk_substeps_extrap(self._h, PREC[precision], _dev(w, ty), float(dt),
+                                           int(n), float(t0), _dev(ua, ty), float(ta),
+                                           _dev(ub, ty), float(tb),
+                                           None if work is None else _dev(work, ty),
+                                           _stream(stream)))
+        return w
+
+    def richardson(self, v, g, u, tau, ds, rtol, max_it, work=None, precision="fp64",
+                   stream=None):
+        """Pseudo-time iteration for v + tau (M^V)^-1 C^V(u) v = g in place on v (the initial
+        guess); returns (number of updates, ||res_0||, last residual norm)."""
+        import torch
+        it = ctypes.c_int(0)
+        res = (ctypes.c_double * 2)()
+        _check(lib().dg_richardson(self._h, PREC[precision], _dev(v, torch.float64),
+                                   _dev(g, torch.float64), _dev(u, torch.float64), float(tau),
+                                   float(ds), float(rtol), int(max_it),
+                                   None if work is None else _dev(work, torch.float64),
+                                   _stream(stream), ctypes.byref(it), res))
+        return it.value, res[0], res[1]
 
     def reduce(self, what, a, b=None, out=None, stream=None):
         import torch

@@ -44,6 +44,7 @@ template <typename T>
 struct ConvArgs {
   const T* x;          // state the operator acts on (neighbour traces are read from it)
   const T* u;          // frozen convecting velocity, or nullptr (u := x)
+  const T* u2;         // second velocity field or nullptr: u(s) = u + uth (u2 - u)
   const T* w0;         // Runge-Kutta base state (mode 1, a != 0)
   T* out;              // mode 0: r;  mode 1: a w0 + b (x + dt r)
   const T* tab;        // reference tables (Shape offsets)
@@ -53,9 +54,30 @@ struct ConvArgs {
   const int* tile_type;// [ntiles]
   const int* type_tab; // [ntypes][D+1]: own table | nbr table << 16
   int ntiles;
-  int mode;
+  int mode;            // 0: r;  1: Runge-Kutta stage;  2: pseudo-time (Richardson) update
   T a, b, dt;
+  T uth;               // time weight of u2 (extrapolated convecting velocity)
+  // mode 2: res = g - x + tau r (g passed as w0), out = x + ds res, and per tile the sum
+  // over its elements of |det J| sum res^2 into partial[tile]; skipped when *stop != 0
+  T tau, ds;
+  const double* absdet;
+  double* partial;
+  const int* stop;
 };
+
+// mode 2 (pseudo-time iteration): sum over the wave of the per-lane partial sums, in a fixed
+// butterfly order (deterministic); every lane of the wave must take part
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// stop flag of an iteration driven from the host (nullptr: none); read once per launch
+__device__ __forceinline__ bool stopped(const int* flag) {
+  return flag && *(const int __attribute__((address_space(4)))*)flag != 0;
+}
+
 
 // scaled outward reference normal n^_f |F^_f| of local facet f (opposite vertex f)
 template <int D, typename T>
@@ -122,6 +144,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
   const int lane = threadIdx.x & 63;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int tile = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
+  if (stopped(A.stop)) return;  // uniform over the grid
   Tabs<SM, T> tab;
   tab.c = (typename Tabs<SM, T>::cptr)A.tab;
   if constexpr (SM != SM_ALL) {
@@ -133,7 +156,10 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
     tab.l = A.tab;
   }
   const int type = __builtin_amdgcn_readfirstlane(A.tile_type[tile]);
-  if (type < 0) return;  // empty tile padding a block
+  if (type < 0) {  // empty tile padding a block
+    if (A.mode == 2 && lane == 0) A.partial[tile] = 0.0;
+    return;
+  }
   const int e_raw = A.elem_list[tile * 64 + lane];
   const int e = e_raw >= 0 ? e_raw : A.elem_list[tile * 64];  // padded lanes redo lane 0
   const ciptr ttab = (ciptr)A.type_tab;
@@ -151,6 +177,13 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
       for (int i = 0; i < D; ++i)
 #pragma unroll
         for (int m = 0; m < NP; ++m) uc[i][m] = pu[i * NP + m];
+      if (A.u2) {
+        const T* __restrict__ pu2 = A.u2 + (size_t)e * D * NP;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int m = 0; m < NP; ++m) uc[i][m] = fma(A.uth, pu2[i * NP + m] - uc[i][m], uc[i][m]);
+      }
     }
     const T* __restrict__ pj = A.jinv + (size_t)e * D * D;
 #pragma unroll
@@ -230,6 +263,13 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
         for (int i = 0; i < D; ++i)
 #pragma unroll
           for (int m = 0; m < NP; ++m) un[i][m] = pu[i * NP + m];
+        if (A.u2) {
+          const T* __restrict__ pu2 = A.u2 + (size_t)ne * D * NP;
+#pragma unroll
+          for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int m = 0; m < NP; ++m) un[i][m] = fma(A.uth, pu2[i * NP + m] - un[i][m], un[i][m]);
+        }
       }
     }
     T Nt[D];
@@ -290,8 +330,29 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
     }
   }
 
-  if (e_raw < 0) return;
   T* o = A.out + (size_t)e * D * NP;
+  if (A.mode == 2) {
+    // every lane takes part in the wave sum; padded lanes store nothing and add zero
+    const T* pg = A.w0 + (size_t)e * D * NP;
+    T gv[D][NP];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int m = 0; m < NP; ++m) gv[i][m] = pg[i * NP + m];
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        const T res = fma(A.tau, R[i][m], gv[i][m] - c[i][m]);
+        if (e_raw >= 0) o[i * NP + m] = fma(A.ds, res, c[i][m]);
+        acc = fma((double)res, (double)res, acc);
+      }
+    acc = wave_sum(e_raw >= 0 ? acc * A.absdet[e] : 0.0);
+    if (lane == 0) A.partial[tile] = acc;
+    return;
+  }
+  if (e_raw < 0) return;
   if (A.mode == 0) {
 #pragma unroll
     for (int i = 0; i < D; ++i)

@@ -2,6 +2,7 @@
 // device tables, operator application, fused SSP-RK3 substeps, reductions.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -238,23 +239,39 @@ dg_status run_apply(const dg_mesh* m, const void* w, const void* u, void* r, hip
   return DG_OK;
 }
 
+// Convecting velocity extrapolated linearly in time from two fields (the propagation problem
+// of Sec. 3.2): u(s) = ua + (s - ta) / (tb - ta) (ub - ua); substep j starts at t0 + j dt.
+struct Extrap {
+  const void* ub;
+  double t0, ta, tb;
+  // time weight of ub at stage time t0 + j dt + c dt (Shu-Osher abscissae c = 0, 1, 1/2)
+  double weight(int j, double dt, double c) const {
+    const double s = t0 + j * dt;
+    return ((c == 0.0 ? s : s + c * dt) - ta) / (tb - ta);
+  }
+};
+
 template <typename T>
 dg_status run_rk(const dg_mesh* m, void* w, double dt, int n, const void* u, void* work,
-                 hipStream_t s) {
+                 hipStream_t s, const Extrap* ex = nullptr) {
   const size_t n_state = (size_t)m->h.E * m->h.dim * m->h.np;
   T* w0 = (T*)w;
   T* w1 = (T*)work;
   T* w2 = w1 + n_state;
   auto a = base_args<T>(m);
   a.u = (const T*)u;
+  a.u2 = ex ? (const T*)ex->ub : nullptr;
   a.mode = 1;
   a.dt = (T)dt;
   for (int it = 0; it < n; ++it) {
     a.x = w0; a.w0 = nullptr; a.out = w1; a.a = T(0); a.b = T(1);
+    if (ex) a.uth = (T)ex->weight(it, dt, 0.0);
     HIP_TRY(launch_conv_any<T>(m, a, s));
     a.x = w1; a.w0 = w0; a.out = w2; a.a = T(0.75); a.b = T(0.25);
+    if (ex) a.uth = (T)ex->weight(it, dt, 1.0);
     HIP_TRY(launch_conv_any<T>(m, a, s));
     a.x = w2; a.w0 = w0; a.out = w0; a.a = T(1.0 / 3.0); a.b = T(2.0 / 3.0);
+    if (ex) a.uth = (T)ex->weight(it, dt, 0.5);
     HIP_TRY(launch_conv_any<T>(m, a, s));
   }
   return DG_OK;
@@ -426,7 +443,7 @@ dg_status run_apply_m(const dg_mesh* m, int engine, const void* w, const void* u
 }
 
 dg_status run_rk_m(const dg_mesh* m, int engine, void* w, double dt, int n, const void* u,
-                   void* work, hipStream_t s) {
+                   void* work, hipStream_t s, const Extrap* ex = nullptr) {
   dg_status st = ensure_frags(m, engine);
   if (st != DG_OK) return st;
   const size_t n_state = (size_t)m->h.E * m->h.dim * m->h.np;
@@ -435,15 +452,129 @@ dg_status run_rk_m(const dg_mesh* m, int engine, void* w, double dt, int n, cons
   double* w2 = w1 + n_state;
   auto a = mbase_args(m, engine);
   a.u = (const double*)u;
+  a.u2 = ex ? (const double*)ex->ub : nullptr;
   a.mode = 1;
   a.dt = dt;
   for (int it = 0; it < n; ++it) {
     a.x = w0; a.w0 = nullptr; a.out = w1; a.a = 0.0; a.b = 1.0;
+    if (ex) a.uth = ex->weight(it, dt, 0.0);
     HIP_TRY(launch_mconv_any(m, engine, a, s));
     a.x = w1; a.w0 = w0; a.out = w2; a.a = 0.75; a.b = 0.25;
+    if (ex) a.uth = ex->weight(it, dt, 1.0);
     HIP_TRY(launch_mconv_any(m, engine, a, s));
     a.x = w2; a.w0 = w0; a.out = w0; a.a = 1.0 / 3.0; a.b = 2.0 / 3.0;
+    if (ex) a.uth = ex->weight(it, dt, 0.5);
     HIP_TRY(launch_mconv_any(m, engine, a, s));
+  }
+  return DG_OK;
+}
+
+// ------------------------------------------------------------------ pseudo-time iteration
+// Device-side control block of the Richardson iteration.  The host enqueues iterations in
+// batches; the check kernel sets `done` at the first iterate whose residual meets the
+// criterion and every later kernel of the batch returns at once, so the iterates stop exactly
+// there without a host round trip per iteration.
+struct RichState {
+  int done, iters;
+  double res0, res_last, unused;
+};
+static_assert(sizeof(RichState) <= 4 * sizeof(double), "control block size");
+
+__global__ void rich_init_kernel(RichState* st) {
+  if (threadIdx.x == 0) {
+    st->done = 0;
+    st->iters = -1;
+    st->res0 = 0.0;
+    st->res_last = 0.0;
+  }
+}
+
+// residual norm of iterate `it` from the per-tile sums (fixed summation order), criterion
+__global__ void __launch_bounds__(kRedBlock)
+rich_check_kernel(int nparts, const double* __restrict__ partial, double rtol, int it,
+                  RichState* st) {
+  if (st->done) return;
+  __shared__ double sh[kRedBlock];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += kRedBlock) v += partial[b];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double res = sqrt(sh[0]);
+    if (it == 0) st->res0 = res;
+    st->res_last = res;
+    if (res <= rtol * (it == 0 ? res : st->res0)) {
+      st->done = 1;
+      st->iters = it;
+    }
+  }
+}
+
+// one Richardson update of x into out for every element, with the residual tile sums
+dg_status rich_update(const dg_mesh* m, int engine, const double* x, const double* g,
+                      const double* u, double* out, double tau, double ds, const int* stop,
+                      hipStream_t s, int* nparts) {
+  if (engine >= 0) {
+    auto a = mbase_args(m, engine);
+    a.x = x; a.u = u; a.w0 = g; a.out = out; a.mode = 2; a.tau = tau; a.ds = ds;
+    a.absdet = m->d_absdet; a.partial = m->d_rich_partial; a.stop = stop;
+    *nparts = m->h.ntiles16;
+    HIP_TRY(launch_mconv_any(m, engine, a, s));
+  } else {
+    auto a = base_args<double>(m);
+    a.x = x; a.u = u; a.w0 = g; a.out = out; a.mode = 2; a.tau = tau; a.ds = ds;
+    a.absdet = m->d_absdet; a.partial = m->d_rich_partial; a.stop = stop;
+    *nparts = m->h.ntiles;
+    HIP_TRY(launch_conv_any<double>(m, a, s));
+  }
+  return DG_OK;
+}
+
+dg_status run_richardson(const dg_mesh* m, int engine, double* v, const double* g,
+                         const double* u, double tau, double ds, double rtol, int max_it,
+                         double* work, hipStream_t s, int* iters_out, double* res_out) {
+  RichState* st = (RichState*)m->d_rich_state;
+  const int* stop = &st->done;
+  double* buf[2] = {v, work};
+  hipLaunchKernelGGL(rich_init_kernel, dim3(1), dim3(64), 0, s, st);
+  HIP_TRY(hipGetLastError());
+  constexpr int kBatch = 8;  // iterations enqueued between host checks
+  RichState h{};
+  int it = 0;
+  while (it < max_it) {
+    const int end = std::min(max_it, it + kBatch);
+    for (; it < end; ++it) {
+      int nparts = 0;
+      dg_status rc = rich_update(m, engine, buf[it & 1], g, u, buf[(it + 1) & 1], tau, ds, stop,
+                                 s, &nparts);
+      if (rc != DG_OK) return rc;
+      hipLaunchKernelGGL(rich_check_kernel, dim3(1), dim3(kRedBlock), 0, s, nparts,
+                         m->d_rich_partial, rtol, it, st);
+      HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipMemcpyAsync(&h, st, sizeof(RichState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h.done) break;
+  }
+  if (max_it == 0) {
+    HIP_TRY(hipMemcpyAsync(&h, st, sizeof(RichState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  // iterate n is in buf[n & 1]: the first meeting the criterion, else the last computed
+  const int n = h.done ? h.iters : max_it;
+  if (n & 1) {
+    const size_t bytes = (size_t)m->h.E * m->h.dim * m->h.np * sizeof(double);
+    HIP_TRY(hipMemcpyAsync(v, work, bytes, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  if (iters_out) *iters_out = n;
+  if (res_out) {
+    res_out[0] = h.res0;
+    res_out[1] = h.res_last;
   }
   return DG_OK;
 }
@@ -492,6 +623,14 @@ dg_status dgi::ensure_device(const dg_mesh* cm) {
       (s = upload(m->h.tile_type16, &m->d_tile_type16)) != DG_OK ||
       (s = upload(zeros, &m->d_partial)) != DG_OK)
     return s;
+  {
+    std::vector<double> rz((size_t)std::max(m->h.ntiles, m->h.ntiles16) + 4, 0.0);
+    std::vector<double> st(4, 0.0);
+    double* pst = nullptr;
+    if ((s = upload(rz, &m->d_rich_partial)) != DG_OK || (s = upload(st, &pst)) != DG_OK)
+      return s;
+    m->d_rich_state = pst;
+  }
   m->on_device = true;
   return DG_OK;
 }
@@ -503,7 +642,7 @@ void free_mesh(dg_mesh* m) {
   if (!m) return;
   void* ptrs[] = {m->d_tab, m->d_tab_f, m->d_jinv, m->d_jinv_f, m->d_absdet, m->d_nbr,
                   m->d_elem_list, m->d_tile_type, m->d_type_tab, m->d_work, m->d_partial,
-                  m->d_elem_list16, m->d_tile_type16, m->d_frag[0], m->d_frag[1], m->d_frag[2]};
+                  m->d_rich_partial, m->d_rich_state, m->d_elem_list16, m->d_tile_type16, m->d_frag[0], m->d_frag[1], m->d_frag[2]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -666,8 +805,9 @@ dg_status dg_convection_apply(const dg_mesh* m, dg_precision prec, const void* w
   }
 }
 
-dg_status dg_rk_substeps(const dg_mesh* m, dg_precision prec, void* w, double dt, int n,
-                         const void* u, void* work, void* stream) {
+namespace {
+dg_status rk_common(const dg_mesh* m, dg_precision prec, void* w, double dt, int n,
+                    const void* u, void* work, void* stream, const Extrap* ex) {
   if (!m || !w) return fail(DG_EINVAL, "null pointer");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be positive and finite");
   if (n < 0) return fail(DG_EINVAL, "n must be >= 0");
@@ -695,9 +835,61 @@ dg_status dg_rk_substeps(const dg_mesh* m, dg_precision prec, void* w, double dt
     work = m->d_work;
   }
   const hipStream_t s = (hipStream_t)stream;
-  if (engine >= 0) return run_rk_m(m, engine, w, dt, n, u, work, s);
-  return prec == DG_FP64 ? run_rk<double>(m, w, dt, n, u, work, s)
-                         : run_rk<float>(m, w, dt, n, u, work, s);
+  if (engine >= 0) return run_rk_m(m, engine, w, dt, n, u, work, s, ex);
+  return prec == DG_FP64 ? run_rk<double>(m, w, dt, n, u, work, s, ex)
+                         : run_rk<float>(m, w, dt, n, u, work, s, ex);
+}
+}  // namespace
+
+dg_status dg_rk_substeps(const dg_mesh* m, dg_precision prec, void* w, double dt, int n,
+                         const void* u, void* work, void* stream) {
+  return rk_common(m, prec, w, dt, n, u, work, stream, nullptr);
+}
+
+dg_status dg_richardson(const dg_mesh* m, dg_precision prec, double* v, const double* g,
+                        const double* u, double tau, double ds, double rtol, int max_it,
+                        double* work, void* stream, int* iters_out, double* res_out) {
+  if (!m || !v || !g || !u) return fail(DG_EINVAL, "null pointer");
+  if (!aligned16(v) || !aligned16(g) || !aligned16(u) || (work && !aligned16(work)))
+    return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
+  if (g == v || u == v || (work && (work == v || work == g || work == u)))
+    return fail(DG_EINVAL, "v must not alias g, u or work");
+  if (!std::isfinite(tau) || !(ds > 0) || !std::isfinite(ds) || !(rtol >= 0) ||
+      !std::isfinite(rtol) || max_it < 0)
+    return fail(DG_EINVAL, "need finite tau, ds > 0, rtol >= 0, max_it >= 0");
+  if (prec == DG_FP32) return fail(DG_EUNSUPPORTED, "the iteration runs on FP64 states");
+  if (prec != DG_FP64 && prec != DG_MIX_F16x2 && prec != DG_MIX_BF16x3)
+    return fail(DG_EINVAL, "unknown precision");
+  dg_status st = ensure_device(m);
+  if (st != DG_OK) return st;
+  const int engine = engine_of(m, prec);
+  if (engine >= 0 && (st = ensure_frags(m, engine)) != DG_OK) return st;
+  if (!work) {
+    std::lock_guard<std::mutex> lock(const_cast<dg_mesh*>(m)->mu);
+    const size_t bytes = 2 * (size_t)m->h.E * m->h.dim * m->h.np * 8 + 16;
+    if (m->work_bytes < bytes) {
+      if (m->d_work) HIP_TRY(hipFree(m->d_work));
+      m->d_work = nullptr;
+      m->work_bytes = 0;
+      HIP_TRY(hipMalloc(&m->d_work, bytes));
+      m->work_bytes = bytes;
+    }
+    work = (double*)m->d_work;
+  }
+  return run_richardson(m, engine, v, g, u, tau, ds, rtol, max_it, work, (hipStream_t)stream,
+                        iters_out, res_out);
+}
+
+dg_status dg_rk_substeps_extrap(const dg_mesh* m, dg_precision prec, void* w, double dt, int n,
+                                double t0, const void* ua, double ta, const void* ub, double tb,
+                                void* work, void* stream) {
+  if (!ua || !ub) return fail(DG_EINVAL, "null velocity field");
+  if (ua == w || ub == w) return fail(DG_EINVAL, "velocity fields must not alias w");
+  if (!aligned16(ub)) return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
+  if (!std::isfinite(t0) || !std::isfinite(ta) || !std::isfinite(tb) || !(tb != ta))
+    return fail(DG_EINVAL, "t0, ta, tb must be finite with tb != ta");
+  const Extrap ex{ub, t0, ta, tb};
+  return rk_common(m, prec, w, dt, n, ua, work, stream, &ex);
 }
 
 dg_status dg_reduce(const dg_mesh* m, int what, const double* a, const double* b,

@@ -40,6 +40,8 @@ struct dg_mesh {
   mutable void* d_work = nullptr;
   mutable size_t work_bytes = 0;
   double* d_partial = nullptr;  // reduction partials
+  double* d_rich_partial = nullptr;  // pseudo-time iteration: per-tile residual sums
+  void* d_rich_state = nullptr;      // pseudo-time iteration: device-side control block
   int n_partial = 0;
   bool on_device = false;
   int tab_src = -1;  // VALU kernel table sources (bit t: table t via scalar loads); -1: default

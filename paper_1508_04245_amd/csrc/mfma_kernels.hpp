@@ -207,6 +207,7 @@ template <typename T>
 struct MArgs {
   const double* x;       // state the operator acts on
   const double* u;       // frozen convecting velocity or nullptr
+  const double* u2;      // second velocity field or nullptr: u(s) = u + uth (u2 - u)
   const double* w0;      // Runge-Kutta base state (mode 1, a != 0)
   double* out;
   const void* frag;      // fragment tables (engine layout)
@@ -216,8 +217,15 @@ struct MArgs {
   const int* tile_type;  // [ntiles], -1 = empty tile
   const int* type_tab;   // [ntypes][D+1]
   int ntiles;
-  int mode;
+  int mode;              // 0: r;  1: Runge-Kutta stage;  2: pseudo-time (Richardson) update
   double a, b, dt;
+  double uth;            // time weight of u2 (extrapolated convecting velocity)
+  // mode 2 as in the VALU kernel: res = g - x + tau r, out = x + ds res, tile sums of
+  // |det J| res^2 into partial[tile]; skipped when *stop != 0
+  double tau, ds;
+  const double* absdet;
+  double* partial;
+  const int* stop;
 };
 
 // B fragments of a state block: element n, component i, K chunk kc
@@ -233,6 +241,20 @@ __device__ __forceinline__ typename E::frag state_frag(const double* p, int i, i
   return E::make_b(v, e);
 }
 
+// B fragments of a velocity block, u + th (u2 - u) when a second field is given
+template <class E, int D, int NP>
+__device__ __forceinline__ typename E::frag vel_frag(const double* p, const double* p2, double th,
+                                                     int i, int kc, int g, int& e) {
+  double v[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = 16 * kc + E::kidx(g, j);
+    v[j] = k < NP ? p[i * NP + k] : 0.0;
+    if (p2 && k < NP) v[j] = fma(th, p2[i * NP + k] - v[j], v[j]);
+  }
+  return E::make_b(v, e);
+}
+
 template <int D, int K, class E, bool SELF>
 __global__ void __launch_bounds__(256) mconv_kernel(MArgs<double> A) {
   using M = MShape<D, K>;
@@ -242,8 +264,12 @@ __global__ void __launch_bounds__(256) mconv_kernel(MArgs<double> A) {
   const int g = lane >> 4, n = lane & 15;
   const int blk = dgk::xcd_block(blockIdx.x, gridDim.x);
   const int tile = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
+  if (dgk::stopped(A.stop)) return;  // uniform over the grid
   const int type = __builtin_amdgcn_readfirstlane(A.tile_type[tile]);
-  if (type < 0) return;
+  if (type < 0) {
+    if (A.mode == 2 && lane == 0) A.partial[tile] = 0.0;
+    return;
+  }
   const int e_raw = A.elem_list[tile * 16 + n];
   const int e = e_raw >= 0 ? e_raw : A.elem_list[tile * 16];
   const double* px = A.x + (size_t)e * D * NP;
@@ -270,7 +296,9 @@ __global__ void __launch_bounds__(256) mconv_kernel(MArgs<double> A) {
 #pragma unroll
     for (int kc = 0; kc < KP; ++kc) {
       cB[i][kc] = state_frag<E, D, NP>(px, i, kc, g, ce[i][kc]);
-      if constexpr (!SELF) uB[i][kc] = state_frag<E, D, NP>(pu, i, kc, g, ue[i][kc]);
+      if constexpr (!SELF)
+        uB[i][kc] = vel_frag<E, D, NP>(pu, A.u2 ? A.u2 + (size_t)e * D * NP : nullptr, A.uth,
+                                       i, kc, g, ue[i][kc]);
     }
 
   // neighbour fragments: in 2D all facets' are loaded up front so the gathers overlap the
@@ -290,7 +318,9 @@ __global__ void __launch_bounds__(256) mconv_kernel(MArgs<double> A) {
         nB[slot][i][kc] = state_frag<E, D, NP>(pnx, i, kc, g, nce[slot][i][kc]);
         if constexpr (!SELF)
           nuB[slot][i][kc] =
-              state_frag<E, D, NP>(A.u + (size_t)ne * D * NP, i, kc, g, nue[slot][i][kc]);
+              vel_frag<E, D, NP>(A.u + (size_t)ne * D * NP,
+                                 A.u2 ? A.u2 + (size_t)ne * D * NP : nullptr, A.uth, i, kc, g,
+                                 nue[slot][i][kc]);
       }
   };
   if constexpr (NPF > 1) {
@@ -435,8 +465,40 @@ __global__ void __launch_bounds__(256) mconv_kernel(MArgs<double> A) {
   }
 
   // ---------------- epilogue: rows m = 16 mt + row(g, r) of element n
-  if (e_raw < 0) return;
   double* o = A.out + (size_t)e * D * NP;
+  if (A.mode == 2) {
+    // rows m of element n held by this lane; padded lanes store nothing and add zero
+    const double* pg = A.w0 + (size_t)e * D * NP;
+    double gv[D][KP][4], cv[D][KP][4];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int mt = 0; mt < KP; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = 16 * mt + E::row(g, r);
+          gv[i][mt][r] = m < NP ? pg[i * NP + m] : 0.0;
+          cv[i][mt][r] = m < NP ? px[i * NP + m] : 0.0;
+        }
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int mt = 0; mt < KP; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = 16 * mt + E::row(g, r);
+          if (m < NP) {
+            const double res = fma(A.tau, R[i][mt][r], gv[i][mt][r] - cv[i][mt][r]);
+            if (e_raw >= 0) o[i * NP + m] = fma(A.ds, res, cv[i][mt][r]);
+            acc = fma(res, res, acc);
+          }
+        }
+    acc = dgk::wave_sum(e_raw >= 0 ? acc * A.absdet[e] : 0.0);
+    if (lane == 0) A.partial[tile] = acc;
+    return;
+  }
+  if (e_raw < 0) return;
   if (A.mode == 0) {
 #pragma unroll
     for (int i = 0; i < D; ++i)

@@ -1,0 +1,104 @@
+"""GPU parity of the pseudo-time (Richardson) iteration for the implicit convection problem
+(dg_richardson) against the oracle's iteration: the same number of updates (an integer, so
+bit-exact), the same residual norms and the same final iterate, on jittered meshes with ragged
+tiles, for the VALU and matrix-core FP64 kernels and the mixed-precision contractions.
+Every test prints its case before touching the GPU.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_common import initial_state, oracle_space, rel_l2, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import paper_1508_04245_amd as dg
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    dg.lib()
+    return dg
+
+
+def lib_mesh(dg, sp, dim, k):
+    X = sp.mesh.X
+    E = X.shape[0]
+    elem = np.arange(E * (dim + 1)).reshape(E, dim + 1)
+    return dg.Mesh.from_arrays(dim, k, X.reshape(-1, dim), elem, np.ones(dim))
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def problem(dim, k, N, jit):
+    sp = oracle_space(dim, N, k, jit, seed=3)
+    g = initial_state(sp, seed=7, sd=0.05)
+    u = 0.5 * initial_state(sp, field="fourier", seed=8)
+    h = 1.0 / N
+    umax = sp.max_speed(u)
+    tau = 0.5 * h / umax
+    ds = 1.0 / (1.0 + tau * (k + 1) ** 2 * umax / h)
+    return sp, g, u, tau, ds
+
+
+CASES = [(2, 2, 13, 0.2), (2, 4, 7, 0.2), (3, 2, 3, 0.15), (3, 3, 3, 0.15)]
+
+
+@pytest.mark.parametrize("dim,k,N,jit", CASES)
+def test_richardson_vs_oracle(dg, dim, k, N, jit):
+    say("case richardson dim=%d k=%d N=%d jitter=%g" % (dim, k, N, jit))
+    sp, g, u, tau, ds = problem(dim, k, N, jit)
+    ref, n_ref, hist = sp.richardson(g, u, tau, ds, RTOL, 1000)
+    r = np.array(hist) / hist[0]
+    # the stopping decision is not borderline, so both sides must take it at the same update
+    assert r[-1] < RTOL * (1 - 1e-6) and r[-2] > RTOL * (1 + 1e-6)
+    for prec, kern in [("fp64", "valu"), ("fp64", "mfma"), ("bf16x3", None), ("f16x2", None)]:
+        if kern:
+            os.environ["DGCONV_FP64_KERNEL"] = kern
+        else:
+            os.environ.pop("DGCONV_FP64_KERNEL", None)
+        say("   %s %s" % (prec, kern or ""))
+        m = lib_mesh(dg, sp, dim, k)
+        v = dev(g)
+        n, res0, res_last = m.richardson(v, dev(g), dev(u), tau, ds, RTOL, 1000, precision=prec)
+        e = rel_l2(sp, v.cpu().numpy(), ref)
+        say("      updates %d (oracle %d)  res0 %.6e (%.6e)  last %.3e  rel_l2 %.3e"
+            % (n, n_ref, res0, hist[0], res_last, e))
+        if prec == "fp64":
+            assert n == n_ref
+            assert abs(res0 - hist[0]) <= 1e-12 * hist[0]
+            assert abs(res_last - hist[-1]) <= 1e-9 * hist[-1]
+            assert e <= 1e-12
+        else:
+            # contractions rounded at about 1e-7 of the operator: the residual history agrees
+            # until it nears that level, so the count may move by a few updates
+            assert abs(n - n_ref) <= 3
+            assert e <= 1e-6
+    os.environ.pop("DGCONV_FP64_KERNEL", None)
+
+
+def test_richardson_edge_cases(dg):
+    say("case richardson edge cases")
+    sp, g, u, tau, ds = problem(2, 2, 5, 0.1)
+    m = lib_mesh(dg, sp, 2, 2)
+    v = dev(g)
+    n, res0, res_last = m.richardson(v, dev(g), dev(u), tau, ds, RTOL, 0)
+    assert n == 0 and torch.equal(v, dev(g))
+    z = dev(np.zeros(sp.shape))
+    v = dev(np.zeros(sp.shape))
+    n, res0, res_last = m.richardson(v, z, dev(u), tau, ds, RTOL, 50)
+    assert n == 0 and res0 == 0.0 and not v.any()
+    # not converged within the limit: the result is the last iterate, as in the oracle
+    ref, n_ref, hist = sp.richardson(g, u, tau, ds, 1e-30, 7)
+    v = dev(g)
+    n, res0, res_last = m.richardson(v, dev(g), dev(u), tau, ds, 1e-30, 7)
+    assert n == n_ref == 7
+    assert rel_l2(sp, v.cpu().numpy(), ref) <= 1e-12
+    with pytest.raises(Exception):
+        m.richardson(v, dev(g), dev(u), tau, ds, RTOL, 10, precision="fp32")

@@ -153,3 +153,29 @@ def test_basis_matches_golden_exact_values(name):
         v, _ = dg.eval_basis(dim, k, pt)
         assert np.abs(v[0] - ref).max() < 1e-14 * max(1.0, np.abs(ref).max())
         assert np.abs(R.eval_basis(dim, k, pt)[0] - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
+
+
+def test_extrap_argument_errors_before_device_work():
+    """Invalid velocity arguments are rejected before any device access."""
+    L = dg.lib()
+    m = dg.Mesh.box(2, 4, 2)
+    w, ua, ub = 4096, 8192, 12288  # never dereferenced: the checks fail first
+    assert L.dg_rk_substeps_extrap(m._h, 0, w, 0.01, 1, 0.0, None, 0.0, ub, 1.0, None, None) == -1
+    assert L.dg_rk_substeps_extrap(m._h, 0, w, 0.01, 1, 0.0, ua, 0.0, None, 1.0, None, None) == -1
+    assert L.dg_rk_substeps_extrap(m._h, 0, w, 0.01, 1, 0.0, ua, 1.0, ub, 1.0, None, None) == -1
+    assert L.dg_rk_substeps_extrap(m._h, 0, w, 0.01, 1, 0.0, w, 0.0, ub, 1.0, None, None) == -1
+    assert L.dg_rk_substeps_extrap(m._h, 0, w, 0.01, 1, float("nan"), ua, 0.0, ub, 1.0, None,
+                                   None) == -1
+
+
+def test_richardson_argument_errors_before_device_work():
+    L = dg.lib()
+    m = dg.Mesh.box(2, 4, 2)
+    v, g, u = 4096, 8192, 12288  # never dereferenced: the checks fail first
+    f = L.dg_richardson
+    assert f(m._h, 0, v, g, None, 0.1, 0.5, 1e-6, 10, None, None, None, None) == -1
+    assert f(m._h, 0, v, v, u, 0.1, 0.5, 1e-6, 10, None, None, None, None) == -1
+    assert f(m._h, 0, v, g, u, 0.1, 0.0, 1e-6, 10, None, None, None, None) == -1
+    assert f(m._h, 0, v, g, u, 0.1, 0.5, -1.0, 10, None, None, None, None) == -1
+    assert f(m._h, 0, v, g, u, 0.1, 0.5, 1e-6, -1, None, None, None, None) == -1
+    assert f(m._h, 1, v, g, u, 0.1, 0.5, 1e-6, 10, None, None, None, None) == -4  # FP32
