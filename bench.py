@@ -31,7 +31,7 @@ TRAFFIC_SOURCES = ("paper_1508_04245_amd/csrc/conv_kernels.hpp",
                    "paper_1508_04245_amd/csrc/mfma_kernels.hpp",
                    "paper_1508_04245_amd/csrc/dgconv.hip")
 MEASURED_TRAFFIC = {
-    ("c2", "fp64", "valu"): (128.3e6, "83db17d191f4380b"),
+    ("c2", "fp64", "valu"): (109.6e6, "1edadeabe8b21c03"),
 }
 
 
@@ -88,13 +88,14 @@ def alg_flops_per_elem(dim, k):
     return interp + uhat + test + trace + lift + flux + rk
 
 
-def alg_bytes_per_elem(dim, k, stage_reads_w0=True, esz=8):
-    """Algorithmic HBM bytes of one fused application per element: read x (neighbours
-    counted once), read w0 (stages 2, 3), write out, geometry (J^-1, neighbour ids, list)."""
+def alg_bytes_per_elem(dim, k, esz=8):
+    """Algorithmic HBM bytes per element of one fused stage launch, averaged over the three
+    SSP-RK3 stages: read x (neighbour states counted once), write out, read w0 in stages 2
+    and 3 only (8/3 states on average), plus geometry (J^-1, neighbour ids, element list)."""
     NP, _, _ = shape_counts(dim, k)
     state = dim * NP * esz
     geo = dim * dim * esz + 4 * (dim + 1) + 4
-    return state * (3 if stage_reads_w0 else 2) + geo
+    return state * 8.0 / 3.0 + geo
 
 
 def make_state(dg, cfg, seed=0):
