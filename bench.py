@@ -46,10 +46,10 @@ def kernel_sources_hash():
 
 def kernel_label(cfg, precision, fp64_kernel):
     """Which operator kernel the library runs (its default: matrix cores for FP64 when the
-    element has >= 20 basis functions per component)."""
+    element has >= 20 basis functions per component, and for 2D P3)."""
     NP, _, _ = shape_counts(cfg["dim"], cfg["k"])
     if precision == "fp64":
-        kind = fp64_kernel or ("mfma" if NP >= 20 else "valu")
+        kind = fp64_kernel or ("mfma" if NP >= 20 or (cfg["dim"], cfg["k"]) == (2, 3) else "valu")
     else:
         kind = "valu" if precision == "fp32" else "mfma"
     name = "conv_kernel" if kind == "valu" else "mconv_kernel"

@@ -678,11 +678,12 @@ dg_status dg_mesh_create(int dim, int k, int64_t n_vert, const double* xyz, int6
     // scalar loads; t = basis values, gradients, own traces, neighbour traces, lifts)
     const char* tm = std::getenv("DGCONV_TABLES");
     if (tm) m->tab_src = std::string(tm) == "lds" ? 0 : std::string(tm) == "smem" ? 31 : std::atoi(tm);
-    // FP64 kernel: matrix cores for large elements (n_basis >= 20: measured 2x faster on 3D
-    // P3), the VALU kernel otherwise (faster on 3D P2, equal on 2D P4);
+    // FP64 kernel, from measurements on MI355X (us per stage launch, VALU / matrix cores):
+    // 3D P3 1360 / 575, 2D P3 15.5 / 13.5, 2D P4 49 / 54, 3D P2 809 / 1005.  Matrix cores
+    // for elements with >= 20 basis functions and for 2D P3, the VALU kernel otherwise;
     // DGCONV_FP64_KERNEL=valu|mfma overrides
     const char* fk = std::getenv("DGCONV_FP64_KERNEL");
-    m->fp64_mfma = fk ? std::string(fk) == "mfma" : m->h.np >= 20;
+    m->fp64_mfma = fk ? std::string(fk) == "mfma" : (m->h.np >= 20 || (dim == 2 && k == 3));
   }
   *out = m;
   return DG_OK;

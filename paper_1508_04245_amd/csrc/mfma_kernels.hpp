@@ -59,11 +59,13 @@ struct EngF64 {
   // K index (within a 16-chunk) of B element j in lane group g; row of accumulator reg r
   __device__ static __forceinline__ int kidx(int g, int j) { return 4 * j + g; }
   __device__ static __forceinline__ int row(int g, int r) { return g + 4 * r; }
-  __device__ static __forceinline__ frag load_a(const void* base, int blk, int lane) {
+  // nk: K sub-chunks of 4 (of the chunk's 4) that hold rows inside the contraction; the
+  // rest are zero padding on both operands and are neither loaded nor multiplied
+  __device__ static __forceinline__ frag load_a(const void* base, int blk, int lane, int nk = 4) {
     const double* p = (const double*)base + (size_t)blk * BLK;
     frag f;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) f.v[j] = p[j * 64 + lane];
+    for (int j = 0; j < 4; ++j) f.v[j] = j < nk ? p[j * 64 + lane] : 0.0;
     return f;
   }
   template <typename V>
@@ -74,10 +76,11 @@ struct EngF64 {
     e = 0;
     return f;
   }
-  // acc += A B  (double accumulator)
-  __device__ static __forceinline__ void mma(d4& acc, const frag& a, const frag& b) {
+  // acc += A B  (double accumulator); nk is wave-uniform, so every lane takes each MFMA
+  __device__ static __forceinline__ void mma(d4& acc, const frag& a, const frag& b, int nk = 4) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[j], b.v[j], acc, 0, 0, 0);
+    for (int j = 0; j < 4; ++j)
+      if (j < nk) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[j], b.v[j], acc, 0, 0, 0);
   }
 };
 
@@ -90,7 +93,7 @@ struct EngSplit {
   struct frag { h_t p[NS]; };
   __device__ static __forceinline__ int kidx(int g, int j) { return 4 * g + j; }
   __device__ static __forceinline__ int row(int g, int r) { return 4 * g + r; }
-  __device__ static __forceinline__ frag load_a(const void* base, int blk, int lane) {
+  __device__ static __forceinline__ frag load_a(const void* base, int blk, int lane, int = 4) {
     const h_t* p = (const h_t*)base + (size_t)blk * BLK;
     frag f;
 #pragma unroll
@@ -142,8 +145,8 @@ struct EngSplit {
     if constexpr (F16) return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
     else return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
   }
-  // acc += A B over the product terms a + b < NS (smallest first)
-  __device__ static __forceinline__ void mma(f4& acc, const frag& a, const frag& b) {
+  // acc += A B over the product terms a + b < NS (smallest first); K = 16 per instruction
+  __device__ static __forceinline__ void mma(f4& acc, const frag& a, const frag& b, int = 4) {
     if constexpr (NS == 3) {
       acc = mm(a.p[1], b.p[1], acc);
       acc = mm(a.p[0], b.p[2], acc);
@@ -160,13 +163,19 @@ struct AccOf { typedef f4 type; };
 template <>
 struct AccOf<EngF64> { typedef d4 type; };
 
+// number of 4-row K sub-chunks of a 16-row chunk that hold rows below n_valid (n_valid = the
+// contraction length minus the chunk's first row)
+__device__ __forceinline__ constexpr int nk_of(int n_valid) {
+  return n_valid >= 16 ? 4 : n_valid <= 0 ? 0 : (n_valid + 3) / 4;
+}
+
 // one K-chunk product folded into an FP64 accumulator: out[r] += 2^e (A B)[r]
 template <class E>
 __device__ __forceinline__ void mma_into(double (&out)[4], const typename E::frag& a,
-                                         const typename E::frag& b, int e) {
+                                         const typename E::frag& b, int e, int nk = 4) {
   if constexpr (!E::SPLIT) {
     d4 acc = {out[0], out[1], out[2], out[3]};  // FP64: chain directly in the accumulator
-    E::mma(acc, a, b);
+    E::mma(acc, a, b, nk);
 #pragma unroll
     for (int r = 0; r < 4; ++r) out[r] = acc[r];
   } else {
@@ -184,9 +193,9 @@ __device__ __forceinline__ void mma_into(double (&out)[4], const typename E::fra
 // around a matrix instruction, which must run with every lane active.
 template <class E, typename V>
 __device__ __forceinline__ void mma_acc(V (&out)[4], const typename E::frag& a,
-                                        const typename E::frag& b, int e) {
+                                        const typename E::frag& b, int e, int nk = 4) {
   if constexpr (!E::SPLIT) {
-    mma_into<E>(out, a, b, e);
+    mma_into<E>(out, a, b, e, nk);
   } else {
     if constexpr (!E::SCALED) {
       f4 acc = {out[0], out[1], out[2], out[3]};
@@ -353,9 +362,10 @@ __global__ void __launch_bounds__(256) mconv_kernel(MArgs<double> A) {
       }
 #pragma unroll
       for (int kc = 0; kc < KP; ++kc) {
-        const auto a = E::load_a(A.frag, M::OFF_BV + qt * KP + kc, lane);
-        mma_acc<E>(W[i], a, cB[i][kc], ce[i][kc]);
-        if constexpr (!SELF) mma_acc<E>(U[i], a, uB[i][kc], ue[i][kc]);
+        const int nkc = nk_of(NP - 16 * kc);
+        const auto a = E::load_a(A.frag, M::OFF_BV + qt * KP + kc, lane, nkc);
+        mma_acc<E>(W[i], a, cB[i][kc], ce[i][kc], nkc);
+        if constexpr (!SELF) mma_acc<E>(U[i], a, uB[i][kc], ue[i][kc], nkc);
       }
     }
     // pointwise: G_ij = w_i (J^-1 u)_j at the 4 points this lane holds
@@ -383,9 +393,10 @@ __global__ void __launch_bounds__(256) mconv_kernel(MArgs<double> A) {
       for (int i = 0; i < D; ++i) gB[i] = E::make_b(G[i][a], ge[i]);
 #pragma unroll
       for (int mt = 0; mt < KP; ++mt) {
-        const auto af = E::load_a(A.frag, M::OFF_DV + (a * KP + mt) * M::QT + qt, lane);
+        const int nkq = nk_of(M::NQ - 16 * qt);
+        const auto af = E::load_a(A.frag, M::OFF_DV + (a * KP + mt) * M::QT + qt, lane, nkq);
 #pragma unroll
-        for (int i = 0; i < D; ++i) mma_acc<E>(Rv[i][mt], af, gB[i], ge[i]);
+        for (int i = 0; i < D; ++i) mma_acc<E>(Rv[i][mt], af, gB[i], ge[i], nkq);
       }
     }
   }
@@ -425,13 +436,14 @@ __global__ void __launch_bounds__(256) mconv_kernel(MArgs<double> A) {
         }
 #pragma unroll
         for (int kc = 0; kc < KP; ++kc) {
-          const auto ao = E::load_a(A.frag, M::OFF_TR + (own * M::FT + ft) * KP + kc, lane);
-          const auto an = E::load_a(A.frag, M::OFF_TR + (nbt * M::FT + ft) * KP + kc, lane);
-          mma_acc<E>(wm[i], ao, cB[i][kc], ce[i][kc]);
-          mma_acc<E>(wp[i], an, nB[slot][i][kc], nce[slot][i][kc]);
+          const int nkc = nk_of(NP - 16 * kc);
+          const auto ao = E::load_a(A.frag, M::OFF_TR + (own * M::FT + ft) * KP + kc, lane, nkc);
+          const auto an = E::load_a(A.frag, M::OFF_TR + (nbt * M::FT + ft) * KP + kc, lane, nkc);
+          mma_acc<E>(wm[i], ao, cB[i][kc], ce[i][kc], nkc);
+          mma_acc<E>(wp[i], an, nB[slot][i][kc], nce[slot][i][kc], nkc);
           if constexpr (!SELF) {
-            mma_acc<E>(um[i], ao, uB[i][kc], ue[i][kc]);
-            mma_acc<E>(up[i], an, nuB[slot][i][kc], nue[slot][i][kc]);
+            mma_acc<E>(um[i], ao, uB[i][kc], ue[i][kc], nkc);
+            mma_acc<E>(up[i], an, nuB[slot][i][kc], nue[slot][i][kc], nkc);
           }
         }
       }
@@ -457,9 +469,10 @@ __global__ void __launch_bounds__(256) mconv_kernel(MArgs<double> A) {
       for (int i = 0; i < D; ++i) fB[i] = E::make_b(F[i], fe[i]);
 #pragma unroll
       for (int mt = 0; mt < KP; ++mt) {
-        const auto al = E::load_a(A.frag, M::OFF_LF + (own * KP + mt) * M::FT + ft, lane);
+        const int nkf = nk_of(M::NFQ - 16 * ft);
+        const auto al = E::load_a(A.frag, M::OFF_LF + (own * KP + mt) * M::FT + ft, lane, nkf);
 #pragma unroll
-        for (int i = 0; i < D; ++i) mma_into<E>(R[i][mt], al, fB[i], fe[i]);
+        for (int i = 0; i < D; ++i) mma_into<E>(R[i][mt], al, fB[i], fe[i], nkf);
       }
     }
   }
