@@ -264,8 +264,15 @@ __device__ __forceinline__ typename E::frag vel_frag(const double* p, const doub
   return E::make_b(v, e);
 }
 
+// occupancy target: two waves per SIMD (<= 256 registers per lane), which the compiler meets
+// without spilling below 35 basis functions in self mode and below 20 with a separate
+// velocity field; larger elements keep one
+template <int D, int K, bool SELF>
+constexpr int mconv_min_waves() { return dgk::Shape<D, K>::NP >= (SELF ? 35 : 20) ? 1 : 2; }
+
 template <int D, int K, class E, bool SELF>
-__global__ void __launch_bounds__(256) mconv_kernel(MArgs<double> A) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mconv_min_waves<D, K, SELF>(), 8)))
+mconv_kernel(MArgs<double> A) {
   using M = MShape<D, K>;
   constexpr int NP = M::NP, KP = M::KP;
   typedef typename std::conditional<E::SPLIT, float, double>::type V;  // pointwise volume type
