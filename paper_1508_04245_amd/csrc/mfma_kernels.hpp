@@ -268,7 +268,7 @@ __device__ __forceinline__ typename E::frag vel_frag(const double* p, const doub
 // without spilling below 35 basis functions in self mode and below 20 with a separate
 // velocity field; larger elements keep one
 template <int D, int K, bool SELF>
-constexpr int mconv_min_waves() { return dgk::Shape<D, K>::NP >= (SELF ? 35 : 20) ? 1 : 2; }
+constexpr int mconv_min_waves() { return dgk::Shape<D, K>::NP >= (SELF ? 35 : 20) ? 1 : (D == 2 && SELF && dgk::Shape<D, K>::NP <= 15 ? 3 : 2); }
 
 template <int D, int K, class E, bool SELF>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mconv_min_waves<D, K, SELF>(), 8)))
@@ -281,6 +281,19 @@ mconv_kernel(MArgs<double> A) {
   const int blk = dgk::xcd_block(blockIdx.x, gridDim.x);
   const int tile = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
   if (dgk::stopped(A.stop)) return;  // uniform over the grid
+  // fragment tables small enough are staged in LDS once per workgroup (every wave of the
+  // block takes part before any of them may leave), larger ones are read from L2
+  constexpr size_t kFragBytes = (size_t)M::NBLK * E::BLK * 8;
+  constexpr bool kFragLds = kFragBytes <= 48 * 1024;
+  __shared__ __attribute__((aligned(16))) char sfrag[kFragLds ? kFragBytes : 16];
+  const void* fr = A.frag;
+  if constexpr (kFragLds) {
+    const uint4* src = (const uint4*)A.frag;
+    uint4* dst = (uint4*)sfrag;
+    for (int i = threadIdx.x; i < (int)(kFragBytes / 16); i += 256) dst[i] = src[i];
+    __syncthreads();
+    fr = sfrag;
+  }
   const int type = __builtin_amdgcn_readfirstlane(A.tile_type[tile]);
   if (type < 0) {
     if (A.mode == 2 && lane == 0) A.partial[tile] = 0.0;
@@ -370,7 +383,7 @@ mconv_kernel(MArgs<double> A) {
 #pragma unroll
       for (int kc = 0; kc < KP; ++kc) {
         const int nkc = nk_of(NP - 16 * kc);
-        const auto a = E::load_a(A.frag, M::OFF_BV + qt * KP + kc, lane, nkc);
+        const auto a = E::load_a(fr, M::OFF_BV + qt * KP + kc, lane, nkc);
         mma_acc<E>(W[i], a, cB[i][kc], ce[i][kc], nkc);
         if constexpr (!SELF) mma_acc<E>(U[i], a, uB[i][kc], ue[i][kc], nkc);
       }
@@ -401,7 +414,7 @@ mconv_kernel(MArgs<double> A) {
 #pragma unroll
       for (int mt = 0; mt < KP; ++mt) {
         const int nkq = nk_of(M::NQ - 16 * qt);
-        const auto af = E::load_a(A.frag, M::OFF_DV + (a * KP + mt) * M::QT + qt, lane, nkq);
+        const auto af = E::load_a(fr, M::OFF_DV + (a * KP + mt) * M::QT + qt, lane, nkq);
 #pragma unroll
         for (int i = 0; i < D; ++i) mma_acc<E>(Rv[i][mt], af, gB[i], ge[i], nkq);
       }
@@ -444,8 +457,8 @@ mconv_kernel(MArgs<double> A) {
 #pragma unroll
         for (int kc = 0; kc < KP; ++kc) {
           const int nkc = nk_of(NP - 16 * kc);
-          const auto ao = E::load_a(A.frag, M::OFF_TR + (own * M::FT + ft) * KP + kc, lane, nkc);
-          const auto an = E::load_a(A.frag, M::OFF_TR + (nbt * M::FT + ft) * KP + kc, lane, nkc);
+          const auto ao = E::load_a(fr, M::OFF_TR + (own * M::FT + ft) * KP + kc, lane, nkc);
+          const auto an = E::load_a(fr, M::OFF_TR + (nbt * M::FT + ft) * KP + kc, lane, nkc);
           mma_acc<E>(wm[i], ao, cB[i][kc], ce[i][kc], nkc);
           mma_acc<E>(wp[i], an, nB[slot][i][kc], nce[slot][i][kc], nkc);
           if constexpr (!SELF) {
@@ -477,7 +490,7 @@ mconv_kernel(MArgs<double> A) {
 #pragma unroll
       for (int mt = 0; mt < KP; ++mt) {
         const int nkf = nk_of(M::NFQ - 16 * ft);
-        const auto al = E::load_a(A.frag, M::OFF_LF + (own * KP + mt) * M::FT + ft, lane, nkf);
+        const auto al = E::load_a(fr, M::OFF_LF + (own * KP + mt) * M::FT + ft, lane, nkf);
 #pragma unroll
         for (int i = 0; i < D; ++i) mma_into<E>(R[i][mt], al, fB[i], fe[i], nkf);
       }
