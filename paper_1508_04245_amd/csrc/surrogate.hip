@@ -80,6 +80,24 @@ __device__ __forceinline__ s4 load4(const uint16_t* p, int64_t row, int64_t rs, 
   return v;
 }
 
+// one epilogue element: C(m, n) = v (+ bias, activation) as the variant asks
+template <int EPI>
+__device__ __forceinline__ void epilogue(const GemmArgs& g, int m, int n, float v) {
+  const int64_t o = (int64_t)m * g.ldc + n;
+  if constexpr (EPI == EPI_BIAS || EPI == EPI_BIAS_GELU) v += g.bias[n];
+  if constexpr (EPI == EPI_BIAS_GELU) {
+    if (g.Cf) g.Cf[o] = v;  // pre-activation, kept for the backward pass
+    g.Cb[o] = f2bf(gelu(v));
+  } else if constexpr (EPI == EPI_GELU_BWD) {
+    v *= gelu_d(g.Z[(int64_t)m * g.ldz + n]);
+    if (g.Cf) g.Cf[o] = v;
+    g.Cb[o] = f2bf(v);
+  } else {
+    if (g.Cf) g.Cf[o] = v;
+    if (g.Cb) g.Cb[o] = f2bf(v);
+  }
+}
+
 template <int EPI>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
   // wave tile 32 (M) x 64 (N): 2 x 4 MFMA tiles; workgroup 4 waves stacked along N (32 x 256)
@@ -113,28 +131,98 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + 16 * i + 4 * g4 + r, n = n0 + 16 * j + c;
-        if (m >= g.M || n >= g.N) continue;
-        float v = acc[i][j][r];
-        const int64_t o = (int64_t)m * g.ldc + n;
-        if constexpr (EPI == EPI_BIAS || EPI == EPI_BIAS_GELU) v += g.bias[n];
-        if constexpr (EPI == EPI_BIAS_GELU) {
-          if (g.Cf) g.Cf[o] = v;  // pre-activation, kept for the backward pass
-          g.Cb[o] = f2bf(gelu(v));
-        } else if constexpr (EPI == EPI_GELU_BWD) {
-          v *= gelu_d(g.Z[(int64_t)m * g.ldz + n]);
-          if (g.Cf) g.Cf[o] = v;
-          g.Cb[o] = f2bf(v);
-        } else {
-          if (g.Cf) g.Cf[o] = v;
-          if (g.Cb) g.Cb[o] = f2bf(v);
-        }
+        if (m < g.M && n < g.N) epilogue<EPI>(g, m, n, acc[i][j][r]);
+      }
+}
+
+// Tiled GEMM for operands contiguous along K (A(m,k) = A[m am + k], B(k,n) = B[n bn + k]: the
+// forward layers, y = x W^T).  Workgroup tile 128 x 128, K step 32; both operand tiles go
+// through LDS (16-byte global loads, double buffered: the next step's loads are in flight
+// during the current step's matrix instructions); 4 waves, each 64 x 64 (4 x 4 MFMA tiles).
+// LDS rows are padded to 40 elements (80 bytes) so the 8-byte operand reads of the 16 rows
+// of a tile fall in distinct banks.
+constexpr int kTBM = 128, kTBN = 128, kTBK = 32, kTLD = kTBK + 8;
+
+template <int EPI>
+__global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t sa[2][kTBM * kTLD];
+  __shared__ __attribute__((aligned(16))) uint16_t sb[2][kTBN * kTLD];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int g4 = lane >> 4, c = lane & 15;
+  const int m0 = blockIdx.y * kTBM, n0 = blockIdx.x * kTBN;
+  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+  // staging: 16-byte chunk q = t + 256 r (r = 0, 1) of a tile is row q / 4, columns 8 (q % 4)
+  uint4 ra[2], rb[2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int q = t + 256 * r, row = q >> 2, k = k0 + (q & 3) * 8;
+      const int mr = m0 + row, nr = n0 + row;
+      ra[r] = (mr < g.M && k < g.K) ? *(const uint4*)(g.A + (int64_t)mr * g.am + k)
+                                    : make_uint4(0, 0, 0, 0);
+      rb[r] = (nr < g.N && k < g.K) ? *(const uint4*)(g.B + (int64_t)nr * g.bn + k)
+                                    : make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int q = t + 256 * r, row = q >> 2, kk = (q & 3) * 8;
+      *(uint4*)(&sa[buf][row * kTLD + kk]) = ra[r];
+      *(uint4*)(&sb[buf][row * kTLD + kk]) = rb[r];
+    }
+  };
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0, 0, 0, 0};
+  const int nk = (g.K + kTBK - 1) / kTBK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int buf = it & 1;
+    if (it + 1 < nk) gload((it + 1) * kTBK);
+#pragma unroll
+    for (int ks = 0; ks < kTBK; ks += 16) {
+      s4 a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = *(const s4*)(&sa[buf][(wm + 16 * i + c) * kTLD + ks + 4 * g4]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = *(const s4*)(&sb[buf][(wn + 16 * j + c) * kTLD + ks + 4 * g4]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    // buf ^ 1 was last read in step it - 1, which every wave finished before the barrier
+    if (it + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * i + 4 * g4 + r, n = n0 + wn + 16 * j + c;
+        if (m < g.M && n < g.N) epilogue<EPI>(g, m, n, acc[i][j][r]);
       }
 }
 
 template <int EPI>
 hipError_t gemm(const GemmArgs& g, hipStream_t s) {
-  const dim3 grid((g.N + 255) / 256, (g.M + 31) / 32);
-  hipLaunchKernelGGL(gemm_kernel<EPI>, grid, dim3(256), 0, s, g);
+  const bool nt = g.ak == 1 && g.bk == 1 && g.am % 8 == 0 && g.bn % 8 == 0 && g.K % 8 == 0 &&
+                  ((uintptr_t)g.A & 15) == 0 && ((uintptr_t)g.B & 15) == 0;
+  if (nt) {
+    const dim3 grid((g.N + kTBN - 1) / kTBN, (g.M + kTBM - 1) / kTBM);
+    hipLaunchKernelGGL(gemm_nt_kernel<EPI>, grid, dim3(256), 0, s, g);
+  } else {
+    const dim3 grid((g.N + 255) / 256, (g.M + 31) / 32);
+    hipLaunchKernelGGL(gemm_kernel<EPI>, grid, dim3(256), 0, s, g);
+  }
   return hipGetLastError();
 }
 
