@@ -79,9 +79,12 @@ class Space:
         m, d = self.mesh, self.dim
         own, nbr = [], []
         for f in range(d + 1):
-            N = m.nbr[T, f]
+            # boundary facets have no neighbour: the own element stands in (values unused)
+            bnd = m.nbr[T, f] < 0
+            N = np.where(bnd, T, m.nbr[T, f])
+            Nf = np.where(bnd, f, m.nbr_facet[T, f])
             own.append(R.eval_basis(d, self.k, self.facet_ref_points(T, f)))
-            nbr.append(R.eval_basis(d, self.k, self.facet_ref_points(N, m.nbr_facet[T, f])))
+            nbr.append(R.eval_basis(d, self.k, self.facet_ref_points(N, Nf)))
         out = (np.stack(own, axis=1), np.stack(nbr, axis=1))
         nbytes = len(T) * (d + 1) * len(self.fw) * self.np * 16
         if nbytes < 1e9 and self._cached_bytes + nbytes < 4e9:
@@ -90,10 +93,40 @@ class Space:
         return out
 
     # ---- the operator ------------------------------------------------------------------
-    def form(self, w, u=None, elems=None):
-        """C_h(u; w, phi_{T,i,m}) for the test functions of elements `elems` -> [n, d, Np]."""
+    def boundary_points(self):
+        """Physical quadrature points of the boundary facets, canonical order: [nb, Qf, d]."""
+        bf = self.mesh.bfacets
+        if len(bf) == 0:
+            return np.zeros((0, len(self.fw), self.dim))
+        out = np.empty((len(bf), len(self.fw), self.dim))
+        for f in range(self.dim + 1):
+            sel = bf[:, 1] == f
+            out[sel] = self.facet_points_phys(bf[sel, 0], f)
+        return out
+
+    def _outer(self, T, f, pnbr, w, vb):
+        """Outer-side values at the points of local facet f of elements T: the neighbour's
+        trace, or on boundary facets the given values vb [nb, Qf, d]."""
+        m = self.mesh
+        N = m.nbr[T, f]
+        bnd = N < 0
+        vals = np.einsum("tqm,tim->tqi", pnbr[:, f], w[np.where(bnd, T, N)])
+        if bnd.any():
+            if vb is None:
+                raise ValueError("the mesh has boundary facets: boundary values are required")
+            vals[bnd] = vb[m.bf_id[T[bnd], f]]
+        return vals
+
+    def form(self, w, u=None, elems=None, wb=None, ub=None):
+        """C_h(u; w, phi_{T,i,m}) for the test functions of elements `elems` -> [n, d, Np].
+
+        Boundary facets (Sec. 2.3: on the inflow part of the boundary the upwind value comes
+        from outside the domain) take the outer values from wb (and the outer convecting
+        velocity from ub in frozen mode, from wb in self mode), given at boundary_points();
+        the flux formula is the interior one with these outer values."""
         m, d = self.mesh, self.dim
         uu = w if u is None else u
+        ubb = wb if u is None else ub
         elems = np.arange(m.E) if elems is None else np.asarray(elems)
         out = np.empty((len(elems), d, self.np))
         for s in range(0, len(elems), self.chunk):
@@ -108,11 +141,10 @@ class Space:
             pown, pnbr = self.facet_basis(T)
             fac = np.zeros_like(vol)
             for f in range(d + 1):
-                N = m.nbr[T, f]
                 wm = np.einsum("tqm,tim->tqi", pown[:, f], w[T])
-                wp = np.einsum("tqm,tim->tqi", pnbr[:, f], w[N])
+                wp = self._outer(T, f, pnbr, w, wb)
                 um = np.einsum("tqm,tim->tqi", pown[:, f], uu[T])
-                up = np.einsum("tqm,tim->tqi", pnbr[:, f], uu[N])
+                up = self._outer(T, f, pnbr, uu, ubb)
                 beta = 0.5 * np.einsum("tqj,tj->tq", um + up, m.normal[T, f])
                 what = np.where(beta[..., None] > 0.0, wm, wp)
                 fac += np.einsum("t,q,tq,tqi,tqm->tim", m.area[T, f], self.fw, beta, what,
@@ -120,18 +152,20 @@ class Space:
             out[s:s + self.chunk] = vol + fac
         return out
 
-    def apply(self, w, u=None, elems=None):
-        """r = -(M^V)^-1 C^V(u) w on elements `elems` (all by default); u=None means u := w."""
+    def apply(self, w, u=None, elems=None, wb=None, ub=None):
+        """r = -(M^V)^-1 C^V(u) w on elements `elems` (all by default); u=None means u := w.
+        wb, ub: boundary values (see form)."""
         elems = np.arange(self.mesh.E) if elems is None else np.asarray(elems)
-        return -self.form(w, u, elems) / self.mass[elems][:, None, :]
+        return -self.form(w, u, elems, wb, ub) / self.mass[elems][:, None, :]
 
-    def ssprk3(self, w, dt, n, u=None):
-        """n substeps of three-stage SSP-RK3 for ds w = apply(w) (Shu-Osher form)."""
+    def ssprk3(self, w, dt, n, u=None, wb=None, ub=None):
+        """n substeps of three-stage SSP-RK3 for ds w = apply(w) (Shu-Osher form), with
+        boundary values held fixed over the substeps."""
         w = np.array(w, dtype=np.float64, copy=True)
         for _ in range(n):
-            w1 = w + dt * self.apply(w, u)
-            w2 = 0.75 * w + 0.25 * (w1 + dt * self.apply(w1, u))
-            w = w / 3.0 + 2.0 / 3.0 * (w2 + dt * self.apply(w2, u))
+            w1 = w + dt * self.apply(w, u, None, wb, ub)
+            w2 = 0.75 * w + 0.25 * (w1 + dt * self.apply(w1, u, None, wb, ub))
+            w = w / 3.0 + 2.0 / 3.0 * (w2 + dt * self.apply(w2, u, None, wb, ub))
         return w
 
     def ssprk3_extrap(self, w, dt, n, t0, ua, ta, ub, tb):
@@ -219,22 +253,23 @@ class Space:
         p, _ = R.collapsed_rule(self.dim, n)
         return float(np.max(np.linalg.norm(self.evaluate(w, p), axis=-1)))
 
-    def dissipation(self, w, u):
-        """1/2 sum_F int_F |beta| |w^- - w^+|^2 ds (each facet once), the upwind dissipation."""
+    def dissipation(self, w, u, wb=None, ub=None):
+        """1/2 sum_F int_F |beta| |w^- - w^+|^2 ds (each facet once), the upwind dissipation;
+        on boundary facets w^+, u^+ are the boundary values wb, ub."""
         m, d = self.mesh, self.dim
         T = np.arange(m.E)
         pown, pnbr = self.facet_basis(T)
         tot = 0.0
         for f in range(d + 1):
-            N = m.nbr[T, f]
             wm = np.einsum("tqm,tim->tqi", pown[:, f], w[T])
-            wp = np.einsum("tqm,tim->tqi", pnbr[:, f], w[N])
+            wp = self._outer(T, f, pnbr, w, wb)
             um = np.einsum("tqm,tim->tqi", pown[:, f], u[T])
-            up = np.einsum("tqm,tim->tqi", pnbr[:, f], u[N])
+            up = self._outer(T, f, pnbr, u, ub)
             beta = 0.5 * np.einsum("tqj,tj->tq", um + up, m.normal[T, f])
             jump2 = np.sum((wm - wp) ** 2, axis=-1)
-            # every facet is visited from both sides: weight 1/2 each
-            tot += 0.5 * np.einsum("t,q,tq,tq->", m.area[T, f], self.fw, np.abs(beta), jump2)
+            # interior facets are visited from both sides (weight 1/2 each), boundary facets once
+            wgt = np.where(m.nbr[T, f] < 0, 1.0, 0.5)
+            tot += np.einsum("t,t,q,tq,tq->", wgt, m.area[T, f], self.fw, np.abs(beta), jump2)
         return 0.5 * tot
 
 

@@ -1,4 +1,4 @@
-"""Periodic affine simplicial meshes for the oracle.
+"""Affine simplicial meshes of a box, periodic or bounded in each direction, for the oracle.
 
 Test infrastructure (see ``oracle/__init__``).
 
@@ -10,7 +10,8 @@ never changed.
 
 Local facet f is the facet opposite local vertex f.  Facets of two elements are matched by
 their centroids modulo the period (a KD-tree with periodic box), so the oracle needs no vertex
-numbering at all.
+numbering at all.  A period entry <= 0 marks a bounded direction: facets left unmatched there
+are boundary facets (nbr = -1), numbered in (element, local facet) order.
 
 Canonical facet orientation: the facet's vertices sorted lexicographically by coordinate.  The
 order is invariant under the periodic translation that relates the two sides, so both sides
@@ -76,23 +77,37 @@ class Mesh:
         self.area = area
         self.canon = canon
         self.canon_idx = canon_idx
-        # match facets by centroid modulo the period
-        flat = cen.reshape(-1, d) % self.period
-        flat = np.where(np.abs(flat - self.period) < 1e-12 * self.period, 0.0, flat)
-        tree = cKDTree(flat, boxsize=self.period)
+        # match facets by centroid modulo the period (bounded directions: no wrap, a box far
+        # larger than the mesh so the tree never wraps them either)
+        per = self.period > 0
+        flat = cen.reshape(-1, d).copy()
+        lo = flat.min(axis=0)
+        ext = flat.max(axis=0) - lo
+        box = np.where(per, self.period, 4.0 * ext + 4.0)
+        flat = np.where(per, flat % np.where(per, self.period, 1.0), flat - lo + ext + 1.0)
+        flat = np.where(per & (np.abs(flat - box) < 1e-12 * box), 0.0, flat)
+        tree = cKDTree(flat, boxsize=box)
         dist, idx = tree.query(flat, k=2)
         hmin = np.min(area) if d == 2 else np.sqrt(np.min(area))
         self_idx = np.arange(flat.shape[0])
         other = np.where(idx[:, 0] == self_idx, idx[:, 1], idx[:, 0])
         dd = np.where(idx[:, 0] == self_idx, dist[:, 1], dist[:, 0])
-        if not np.all(dd < 1e-8 * hmin):
+        matched = dd < 1e-8 * hmin
+        if per.all() and not matched.all():
             raise ValueError("unmatched facet: mesh is not periodic-conforming")
-        if not np.all(other[other] == self_idx):
-            raise ValueError("non-manifold facet matching")
-        self.nbr = (other // nf).reshape(E, nf)
-        self.nbr_facet = (other % nf).reshape(E, nf)
+        # a facet's nearest other facet must match it back, else it lies on the boundary
+        matched &= other[np.where(matched, other, self_idx)] == self_idx
+        other = np.where(matched, other, -1)
+        self.nbr = np.where(matched, other // nf, -1).reshape(E, nf)
+        self.nbr_facet = np.where(matched, other % nf, -1).reshape(E, nf)
+        # boundary facets in (element, local facet) order
+        self.bfacets = np.argwhere(~matched.reshape(E, nf))  # [nb, 2]: (T, f)
+        self.bf_id = np.full((E, nf), -1, dtype=np.int64)
+        self.bf_id[self.bfacets[:, 0], self.bfacets[:, 1]] = np.arange(len(self.bfacets))
         # periodic shift taking the neighbour's unwrapped frame onto ours: x_own = x_nbr + shift
-        self.shift = cen - cen[self.nbr, self.nbr_facet]
+        Nn = np.where(self.nbr >= 0, self.nbr, np.arange(E)[:, None])
+        Ff = np.where(self.nbr >= 0, self.nbr_facet, np.arange(nf)[None, :])
+        self.shift = cen - cen[Nn, Ff]
         self.h = hmin
 
 
@@ -126,24 +141,36 @@ def _lex_sort_vertices(V, rtol=1e-10):
     return out, order
 
 
-def box_mesh(dim, N, jitter=0.0, seed=0):
-    """Periodic unit box, N^d squares split in 2 triangles / cubes split in 6 tetrahedra.
+def box_mesh(dim, N, jitter=0.0, seed=0, periodic=None):
+    """Unit box, N^d squares split in 2 triangles / cubes split in 6 tetrahedra; periodic in
+    every direction unless `periodic` (one flag per direction) says otherwise.
 
     2D: square (i,j) -> lower (v00, v10, v11), id 2(jN+i); upper (v11, v01, v00), id 2(jN+i)+1.
     3D: cube (i,j,l), index (lN+j)N+i, Kuhn split along v000 -> v111: tet s = (v000,
         v000+e_s0, v000+e_s0+e_s1, v111) for the permutations s of (x,y,z) in lexicographic
         order; id 6*cube + index(s).
     `jitter` > 0 displaces every lattice vertex by a seeded periodic random offset of that
-    size times h (identified vertices move together), giving a general affine mesh.
+    size times h (identified vertices move together), giving a general affine mesh; vertices
+    on a bounded side stay on it.
     """
+    periodic = np.ones(dim, dtype=bool) if periodic is None else np.asarray(periodic, bool)
     h = 1.0 / N
     rng = np.random.default_rng(seed)
-    off = rng.uniform(-1, 1, size=(N,) * dim + (dim,)) * jitter * h if jitter else None
+    shape = tuple(N if periodic[a] else N + 1 for a in range(dim))
+    off = rng.uniform(-1, 1, size=shape + (dim,)) * jitter * h if jitter else None
+    if off is not None:
+        for a in range(dim):
+            if not periodic[a]:  # keep the bounded sides straight
+                sl = [slice(None)] * dim
+                sl[a] = 0
+                off[tuple(sl) + (a,)] = 0.0
+                sl[a] = N
+                off[tuple(sl) + (a,)] = 0.0
 
     def vert(idx):  # idx: [..., dim] integer lattice coordinates (unwrapped)
         x = idx * h
         if off is not None:
-            w = np.mod(idx, N)
+            w = np.where(periodic, np.mod(idx, N), idx)
             x = x + off[tuple(w[..., a] for a in range(dim))]
         return x
 
@@ -164,4 +191,4 @@ def box_mesh(dim, N, jitter=0.0, seed=0):
             e0, e1 = eye[s[0]], eye[s[1]]
             tets.append(np.stack([base, base + e0, base + e0 + e1, base + 1], axis=1))
         lat = np.stack(tets, axis=1).reshape(-1, 4, 3)
-    return Mesh(vert(lat), np.ones(dim))
+    return Mesh(vert(lat), np.where(periodic, 1.0, 0.0))
