@@ -59,24 +59,29 @@ typedef struct dg_mesh dg_mesh; /* opaque; immutable after creation */
 
 typedef struct {
   int dim, k, n_basis;      /* n_basis = C(k+dim, dim) per component */
-  int64_t n_elem, n_facet;  /* n_facet = n_elem (dim+1) / 2 */
+  int64_t n_elem, n_facet;  /* n_facet = (n_elem (dim+1) + n_bfacet) / 2 */
   int64_t n_dof;            /* n_elem * dim * n_basis */
   int nq_vol, nq_facet;     /* quadrature points per element volume / per facet */
   int n_types, n_tiles;     /* element classes with identical facet tables; 64-wide tiles */
   double h_min;             /* smallest facet measure (2D) or its square root (3D) */
   double volume;            /* sum of element volumes */
+  int64_t n_bfacet;         /* boundary facets (0 on a fully periodic mesh) */
 } dg_mesh_info;
 
-/* Create a periodic mesh of affine simplices (synchronous, host only).  The device tables
- * are uploaded to the current HIP device by the first compute call (dg_convection_apply,
+/* Create a mesh of affine simplices (synchronous, host only).  The device tables are
+ * uploaded to the current HIP device by the first compute call (dg_convection_apply,
  * dg_rk_substeps, dg_reduce), synchronously; later compute calls must run with the same
  * device current.  xyz: host [n_vert][dim]; elem: host [n_elem][dim+1] vertex ids, local
- * order = element frame; period: host [dim] box lengths (required: every facet must be
- * matched by a facet of another element, modulo the period).  Facets are matched by centroid
- * modulo the period.  k: 0..6 in 2D, 0..4 in 3D.
+ * order = element frame; period: host [dim], per direction either a box length (> 0: facets
+ * are matched by centroid modulo that period) or <= 0 for a bounded direction.  With every
+ * direction periodic, every facet must be matched by a facet of another element; with a
+ * bounded direction, facets left unmatched are boundary facets (Sec. 2.3: where the flow
+ * enters, the upwind value comes from outside the domain), numbered in (element, local
+ * facet) order, and the compute calls take their outer values (the _bc entry points).
+ * k: 0..6 in 2D, 0..4 in 3D.
  * Errors: DG_EINVAL (dim not 2/3, k out of range, null pointers, vertex id out of range),
- * DG_EMESH (|det J| <= 1e-12 h^dim, unmatched or non-manifold facet),
- * DG_ENOMEM, DG_EDEVICE.  *out is set only on success; free with dg_mesh_destroy. */
+ * DG_EMESH (|det J| <= 1e-12 h^dim, unmatched facet on a fully periodic mesh, non-manifold
+ * facet), DG_ENOMEM, DG_EDEVICE.  *out is set only on success; free with dg_mesh_destroy. */
 dg_status dg_mesh_create(int dim, int k, int64_t n_vert, const double* xyz, int64_t n_elem,
                          const int64_t* elem, const double* period, dg_mesh** out);
 
@@ -95,7 +100,8 @@ dg_status dg_mesh_get_info(const dg_mesh* mesh, dg_mesh_info* out);
 dg_status dg_mesh_get_vertices(const dg_mesh* mesh, double* xyz_out);
 
 /* Facet connectivity, host [n_elem][dim+1] each: neighbour element across local facet f
- * (the facet opposite local vertex f) and that facet's local index in the neighbour. */
+ * (the facet opposite local vertex f) and that facet's local index in the neighbour.  On a
+ * boundary facet b the neighbour entry is -1 - b and the facet index -1. */
 dg_status dg_mesh_get_neighbors(const dg_mesh* mesh, int32_t* nbr_out, int32_t* nbr_facet_out);
 
 /* L2 projection onto the DG space (synchronous, host).  dg_project_points writes the
@@ -105,12 +111,34 @@ dg_status dg_mesh_get_neighbors(const dg_mesh* mesh, int32_t* nbr_out, int32_t* 
 dg_status dg_project_points(const dg_mesh* mesh, int n, double* xyz_out);
 dg_status dg_project(const dg_mesh* mesh, int n, const double* vals, double* coef_out);
 
-/* r = -(M^V)^-1 C^V(u) w  (one operator application).
+/* r = -(M^V)^-1 C^V(u) w  (one operator application).  Meshes with boundary facets need
+ * dg_convection_apply_bc (DG_EINVAL here); the same holds for dg_rk_substeps, and
+ * dg_rk_substeps_extrap and dg_richardson run on fully periodic meshes only
+ * (DG_EUNSUPPORTED).
  * w: dev state; u: dev state (frozen convecting velocity) or NULL for u := w (the nonlinear
  * self-convection div(w (x) w)); r: dev state, output.  State element type is double except
  * for DG_FP32 (float).  r must not overlap w or u. */
 dg_status dg_convection_apply(const dg_mesh* mesh, dg_precision prec, const void* w,
                               const void* u, void* r, void* stream);
+
+/* Physical quadrature points of the boundary facets (host, synchronous): xyz_out host
+ * [n_bfacet][nq_facet][dim], in boundary-facet order and, per facet, in the order of the
+ * facet rule on the facet's vertices sorted lexicographically by coordinate (the order the
+ * kernels use).  Outer values wb/ub are given at these points.  Nothing is written when the
+ * mesh has no boundary facets (xyz_out may then be NULL). */
+dg_status dg_boundary_points(const dg_mesh* mesh, double* xyz_out);
+
+/* dg_convection_apply on a mesh with boundary facets (Sec. 2.3, upwind value from outside on
+ * the inflow part of the boundary).  wb: dev [n_bfacet][nq_facet][dim], the outer values of
+ * w at dg_boundary_points (same element type as w); ub: the outer values of the convecting
+ * velocity there, required in frozen mode (u != NULL), ignored in self mode (u := w, so the
+ * outer velocity is wb).  A boundary facet takes the interior flux formula with these outer
+ * values: beta = 1/2 (u^- + u_b).n, F = beta {w} + |beta|/2 (w^- - w_b), so outflow facets
+ * take w^- and inflow facets w_b.  On a mesh without boundary facets wb and ub may be NULL.
+ * Errors as dg_convection_apply, plus DG_EINVAL for a missing wb or ub. */
+dg_status dg_convection_apply_bc(const dg_mesh* mesh, dg_precision prec, const void* w,
+                                 const void* u, const void* wb, const void* ub, void* r,
+                                 void* stream);
 
 /* n substeps of three-stage SSP-RK3 (Shu-Osher) with step dt for ds w = r(w), in place:
  *   w1 = w + dt r(w);  w2 = 3/4 w + 1/4 (w1 + dt r(w1));  w <- 1/3 w + 2/3 (w2 + dt r(w2)).
@@ -140,6 +168,12 @@ dg_status dg_rk_substeps(const dg_mesh* mesh, dg_precision prec, void* w, double
 dg_status dg_richardson(const dg_mesh* mesh, dg_precision prec, double* v, const double* g,
                         const double* u, double tau, double ds, double rtol, int max_it,
                         double* work, void* stream, int* iters_out, double* res_out);
+
+/* dg_rk_substeps on a mesh with boundary facets, the outer values wb, ub (as in
+ * dg_convection_apply_bc) held fixed over the n substeps. */
+dg_status dg_rk_substeps_bc(const dg_mesh* mesh, dg_precision prec, void* w, double dt, int n,
+                            const void* u, const void* wb, const void* ub, void* work,
+                            void* stream);
 
 /* The propagation problem of Sec. 3.2 ("The propagation operator", eq. explproblem): n
  * SSP-RK3 substeps as dg_rk_substeps, with the convecting velocity extrapolated linearly in

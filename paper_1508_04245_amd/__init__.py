@@ -32,7 +32,8 @@ class _Info(ctypes.Structure):
                 ("n_elem", ctypes.c_int64), ("n_facet", ctypes.c_int64),
                 ("n_dof", ctypes.c_int64), ("nq_vol", ctypes.c_int), ("nq_facet", ctypes.c_int),
                 ("n_types", ctypes.c_int), ("n_tiles", ctypes.c_int),
-                ("h_min", ctypes.c_double), ("volume", ctypes.c_double)]
+                ("h_min", ctypes.c_double), ("volume", ctypes.c_double),
+                ("n_bfacet", ctypes.c_int64)]
 
 
 def lib():
@@ -56,6 +57,9 @@ def lib():
         "dg_convection_apply": [P, I, P, P, P, P],
         "dg_rk_substeps": [P, I, P, D, I, P, P, P],
         "dg_rk_substeps_extrap": [P, I, P, D, I, D, P, D, P, D, P, P],
+        "dg_boundary_points": [P, P],
+        "dg_convection_apply_bc": [P, I, P, P, P, P, P, P],
+        "dg_rk_substeps_bc": [P, I, P, D, I, P, P, P, P, P],
         "dg_richardson": [P, I, P, P, P, D, D, D, I, P, P, P, P],
         "dg_reduce": [P, I, P, P, P, P],
         "dg_eval_basis": [I, I, I64, P, P, P],
@@ -176,6 +180,13 @@ class Mesh:
         _check(lib().dg_project(self._h, n, _ptr(vals), _ptr(out)))
         return out
 
+    def boundary_points(self):
+        """Physical quadrature points of the boundary facets: [n_bfacet, nq_facet, dim]."""
+        nb = self.info["n_bfacet"]
+        out = np.zeros((nb, self.info["nq_facet"], self.dim))
+        _check(lib().dg_boundary_points(self._h, _ptr(out) if nb else None))
+        return out
+
     # ---- device calls
     def apply(self, w, u=None, out=None, precision="fp64", stream=None):
         """r = -(M^V)^-1 C^V(u) w on the device (u=None: self-convection)."""
@@ -187,6 +198,30 @@ class Mesh:
                                          None if u is None else _dev(u, dt), _dev(out, dt),
                                          _stream(stream)))
         return out
+
+    def apply_bc(self, w, wb, u=None, ub=None, out=None, precision="fp64", stream=None):
+        """apply on a mesh with boundary facets; wb, ub: outer values [n_bfacet, nq_facet, d]."""
+        import torch
+        dt = torch.float32 if precision == "fp32" else torch.float64
+        if out is None:
+            out = torch.empty_like(w)
+        _check(lib().dg_convection_apply_bc(self._h, PREC[precision], _dev(w, dt),
+                                            None if u is None else _dev(u, dt), _dev(wb, dt),
+                                            None if ub is None else _dev(ub, dt), _dev(out, dt),
+                                            _stream(stream)))
+        return out
+
+    def rk_substeps_bc(self, w, dt, n, wb, u=None, ub=None, work=None, precision="fp64",
+                       stream=None):
+        """n SSP-RK3 substeps in place on a mesh with boundary facets (outer values fixed)."""
+        import torch
+        ty = torch.float32 if precision == "fp32" else torch.float64
+        _check(lib().dg_rk_substeps_bc(self._h, PREC[precision], _dev(w, ty), float(dt), int(n),
+                                       None if u is None else _dev(u, ty), _dev(wb, ty),
+                                       None if ub is None else _dev(ub, ty),
+                                       None if work is None else _dev(work, ty),
+                                       _stream(stream)))
+        return w
 
     def rk_substeps(self, w, dt, n, u=None, work=None, precision="fp64", stream=None):
         """n SSP-RK3 substeps in place on w."""

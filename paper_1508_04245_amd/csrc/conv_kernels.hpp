@@ -44,6 +44,8 @@ template <typename T>
 struct ConvArgs {
   const T* x;          // state the operator acts on (neighbour traces are read from it)
   const T* u;          // frozen convecting velocity, or nullptr (u := x)
+  const T* wb;         // outer values at the boundary facet points [nbf][NFQ][D] (or nullptr)
+  const T* ub;         // outer convecting velocity there (frozen mode)
   const T* u2;         // second velocity field or nullptr: u(s) = u + uth (u2 - u)
   const T* w0;         // Runge-Kutta base state (mode 1, a != 0)
   T* out;              // mode 0: r;  mode 1: a w0 + b (x + dt r)
@@ -103,6 +105,8 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
 // lane, so those reads cost LDS bandwidth per lane).  Splitting the tables between the two
 // paths keeps the LDS return bandwidth below the FP64 FMA rate.
 enum { TB_BV = 0, TB_DV = 1, TB_TRO = 2, TB_TRN = 3, TB_LF = 4 };
+// neighbour-table index that marks a boundary facet in the per-class facet table list
+constexpr int kBoundaryTable = 0x7fff;
 constexpr int SM_ALL = 31;
 
 template <int SM, typename T>
@@ -135,7 +139,7 @@ __device__ __forceinline__ void stage_tables(T* stab, const T* tab) {
 template <int D, int K, typename T>
 constexpr int min_waves() { return Shape<D, K>::NP * D * sizeof(T) <= 15 * 2 * 8 ? 2 : 1; }
 
-template <int D, int K, typename T, bool SELF, int SM>
+template <int D, int K, typename T, bool SELF, int SM, bool BND>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvArgs<T> A) {
   using S = Shape<D, K>;
@@ -247,9 +251,67 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
     const int own = __builtin_amdgcn_readfirstlane(tt & 0xffff);
     const int nbt = __builtin_amdgcn_readfirstlane(tt >> 16);
     const int tro = S::OFF_TR + own * S::NFQ * NP;
-    const int trn = S::OFF_TR + nbt * S::NFQ * NP;
     const int lfo = S::OFF_LF + own * S::NFQ * NP;
     const int ne = A.nbr[(size_t)e * (D + 1) + f];
+    T Nt[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T s = T(0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) s = fma(ji[a][j], nref<D, T>(f, a), s);
+      Nt[j] = s;
+    }
+    // upwind flux at facet point q from the inner and outer traces, lifted into R
+    auto flux_lift = [&](int q, const T (&wm)[D], const T (&wp)[D], const T (&um)[D],
+                         const T (&up)[D]) {
+      T bb = T(0);
+#pragma unroll
+      for (int j = 0; j < D; ++j) bb = fma(um[j] + up[j], Nt[j], bb);
+      // b = bb / 2;  F = b (wm + wp) / 2 + |b| (wm - wp) / 2
+      const T hb = T(0.25) * bb;
+      const T ha = T(0.25) * fabs(bb);
+      T F[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) F[i] = hb * (wm[i] + wp[i]) + ha * (wm[i] - wp[i]);
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        const T l = tab.template get<TB_LF>(lfo + q * NP + m);
+#pragma unroll
+        for (int i = 0; i < D; ++i) R[i][m] = fma(-l, F[i], R[i][m]);
+      }
+    };
+    if (BND && nbt == kBoundaryTable) {
+      // boundary facet (the class fixes it for the whole tile; compiled only for meshes that
+      // have boundary facets): the outer values are the given boundary data at the facet
+      // points, [boundary facet][point][component]
+      const size_t bf = (size_t)(-1 - ne);
+      const T* __restrict__ pb = A.wb + bf * S::NFQ * D;
+      const T* __restrict__ pub = SELF ? pb : A.ub + bf * S::NFQ * D;
+#pragma unroll 1
+      for (int q = 0; q < S::NFQ; ++q) {
+        T wm[D], wp[D], um[D], up[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) { wm[i] = T(0); um[i] = T(0); }
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+          const T to = tab.template get<TB_TRO>(tro + q * NP + m);
+#pragma unroll
+          for (int i = 0; i < D; ++i) {
+            wm[i] = fma(to, c[i][m], wm[i]);
+            if constexpr (!SELF) um[i] = fma(to, uc[i][m], um[i]);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          wp[i] = pb[q * D + i];
+          up[i] = pub[q * D + i];
+          if constexpr (SELF) um[i] = wm[i];
+        }
+        flux_lift(q, wm, wp, um, up);
+      }
+      continue;
+    }
+    const int trn = S::OFF_TR + nbt * S::NFQ * NP;
     T cn[D][NP], un[SELF ? 1 : D][SELF ? 1 : NP];
     {
       const T* __restrict__ p = A.x + (size_t)ne * D * NP;
@@ -271,14 +333,6 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
             for (int m = 0; m < NP; ++m) un[i][m] = fma(A.uth, pu2[i * NP + m] - un[i][m], un[i][m]);
         }
       }
-    }
-    T Nt[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      T s = T(0);
-#pragma unroll
-      for (int a = 0; a < D; ++a) s = fma(ji[a][j], nref<D, T>(f, a), s);
-      Nt[j] = s;
     }
 #pragma unroll 1
     for (int q = 0; q < S::NFQ; ++q) {
@@ -304,7 +358,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
 #pragma unroll
         for (int m = 0; m < NP; ++m) {
           const T to = tab.template get<TB_TRO>(tro + q * NP + m);
-        const T tn = tab.template get<TB_TRN>(trn + q * NP + m);
+          const T tn = tab.template get<TB_TRN>(trn + q * NP + m);
 #pragma unroll
           for (int i = 0; i < D; ++i) {
             um[i] = fma(to, uc[i][m], um[i]);
@@ -312,21 +366,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
           }
         }
       }
-      T bb = T(0);
-#pragma unroll
-      for (int j = 0; j < D; ++j) bb = fma(um[j] + up[j], Nt[j], bb);
-      // b = bb / 2;  F = b (wm + wp) / 2 + |b| (wm - wp) / 2
-      const T hb = T(0.25) * bb;
-      const T ha = T(0.25) * fabs(bb);
-      T F[D];
-#pragma unroll
-      for (int i = 0; i < D; ++i) F[i] = hb * (wm[i] + wp[i]) + ha * (wm[i] - wp[i]);
-#pragma unroll
-      for (int m = 0; m < NP; ++m) {
-        const T l = tab.template get<TB_LF>(lfo + q * NP + m);
-#pragma unroll
-        for (int i = 0; i < D; ++i) R[i][m] = fma(-l, F[i], R[i][m]);
-      }
+      flux_lift(q, wm, wp, um, up);
     }
   }
 

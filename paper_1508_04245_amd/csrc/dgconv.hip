@@ -162,9 +162,9 @@ constexpr int default_tab_src() {
   return 0;
 }
 
-template <int D, int K, typename T, bool SELF, int SM>
+template <int D, int K, typename T, bool SELF, int SM, bool BND = false>
 void launch_conv_sm(const dgk::ConvArgs<T>& a, dim3 grid, hipStream_t s) {
-  hipLaunchKernelGGL((dgk::conv_kernel<D, K, T, SELF, SM>), grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL((dgk::conv_kernel<D, K, T, SELF, SM, BND>), grid, dim3(256), 0, s, a);
 }
 
 template <int D, int K, typename T, bool SELF>
@@ -177,6 +177,10 @@ hipError_t launch_conv_dk(const dg_mesh* m, const dgk::ConvArgs<T>& a, hipStream
   const dim3 grid((m->h.ntiles + 3) / 4);
   // DGCONV_TABLES may pick another split for the FP64 self kernel: every table in LDS (0),
   // every table through scalar loads (31), or the 2D P4 default (21)
+  if (m->h.nbf > 0) {  // meshes with boundary facets: the variant that handles them
+    launch_conv_sm<D, K, T, SELF, kDef, true>(a, grid, s);
+    return hipGetLastError();
+  }
   const int src = m->tab_src < 0 || !dgk::tables_in_lds<D, K, T>() ? kDef : m->tab_src;
   if constexpr (dgk::tables_in_lds<D, K, T>() && SELF && sizeof(T) == 8) {
     if (src != kDef) {
@@ -228,11 +232,19 @@ dgk::ConvArgs<T> base_args(const dg_mesh* m) {
   return a;
 }
 
+// outer values at the boundary facet points (meshes with bounded directions)
+struct Bnd {
+  const void* wb;
+  const void* ub;
+};
+
 template <typename T>
-dg_status run_apply(const dg_mesh* m, const void* w, const void* u, void* r, hipStream_t s) {
+dg_status run_apply(const dg_mesh* m, const void* w, const void* u, void* r, hipStream_t s,
+                    const Bnd* bc = nullptr) {
   auto a = base_args<T>(m);
   a.x = (const T*)w;
   a.u = (const T*)u;
+  if (bc) { a.wb = (const T*)bc->wb; a.ub = (const T*)bc->ub; }
   a.out = (T*)r;
   a.mode = 0;
   HIP_TRY(launch_conv_any<T>(m, a, s));
@@ -253,7 +265,7 @@ struct Extrap {
 
 template <typename T>
 dg_status run_rk(const dg_mesh* m, void* w, double dt, int n, const void* u, void* work,
-                 hipStream_t s, const Extrap* ex = nullptr) {
+                 hipStream_t s, const Extrap* ex = nullptr, const Bnd* bc = nullptr) {
   const size_t n_state = (size_t)m->h.E * m->h.dim * m->h.np;
   T* w0 = (T*)w;
   T* w1 = (T*)work;
@@ -261,6 +273,7 @@ dg_status run_rk(const dg_mesh* m, void* w, double dt, int n, const void* u, voi
   auto a = base_args<T>(m);
   a.u = (const T*)u;
   a.u2 = ex ? (const T*)ex->ub : nullptr;
+  if (bc) { a.wb = (const T*)bc->wb; a.ub = (const T*)bc->ub; }
   a.mode = 1;
   a.dt = (T)dt;
   for (int it = 0; it < n; ++it) {
@@ -382,7 +395,10 @@ hipError_t launch_mconv_dk(const dg_mesh* m, const dgm::MArgs<double>& a, hipStr
   if ((size_t)m->h.elem_list16.size() != (size_t)m->h.ntiles16 * 16 || m->h.ntiles16 % 4)
     return hipErrorInvalidValue;
   const dim3 grid(m->h.ntiles16 / 4), block(256);
-  hipLaunchKernelGGL((dgm::mconv_kernel<D, K, E, SELF>), grid, block, 0, s, a);
+  if (m->h.nbf > 0)  // meshes with boundary facets: the variant that handles them
+    hipLaunchKernelGGL((dgm::mconv_kernel<D, K, E, SELF, true>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((dgm::mconv_kernel<D, K, E, SELF, false>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
@@ -430,12 +446,13 @@ int engine_of(const dg_mesh* m, dg_precision prec) {
 }
 
 dg_status run_apply_m(const dg_mesh* m, int engine, const void* w, const void* u, void* r,
-                      hipStream_t s) {
+                      hipStream_t s, const Bnd* bc = nullptr) {
   dg_status st = ensure_frags(m, engine);
   if (st != DG_OK) return st;
   auto a = mbase_args(m, engine);
   a.x = (const double*)w;
   a.u = (const double*)u;
+  if (bc) { a.wb = (const double*)bc->wb; a.ub = (const double*)bc->ub; }
   a.out = (double*)r;
   a.mode = 0;
   HIP_TRY(launch_mconv_any(m, engine, a, s));
@@ -443,7 +460,8 @@ dg_status run_apply_m(const dg_mesh* m, int engine, const void* w, const void* u
 }
 
 dg_status run_rk_m(const dg_mesh* m, int engine, void* w, double dt, int n, const void* u,
-                   void* work, hipStream_t s, const Extrap* ex = nullptr) {
+                   void* work, hipStream_t s, const Extrap* ex = nullptr,
+                   const Bnd* bc = nullptr) {
   dg_status st = ensure_frags(m, engine);
   if (st != DG_OK) return st;
   const size_t n_state = (size_t)m->h.E * m->h.dim * m->h.np;
@@ -453,6 +471,7 @@ dg_status run_rk_m(const dg_mesh* m, int engine, void* w, double dt, int n, cons
   auto a = mbase_args(m, engine);
   a.u = (const double*)u;
   a.u2 = ex ? (const double*)ex->ub : nullptr;
+  if (bc) { a.wb = (const double*)bc->wb; a.ub = (const double*)bc->ub; }
   a.mode = 1;
   a.dt = dt;
   for (int it = 0; it < n; ++it) {
@@ -723,7 +742,8 @@ dg_status dg_mesh_get_info(const dg_mesh* m, dg_mesh_info* out) {
   out->k = m->h.k;
   out->n_basis = m->h.np;
   out->n_elem = m->h.E;
-  out->n_facet = m->h.E * (m->h.dim + 1) / 2;
+  out->n_facet = (m->h.E * (m->h.dim + 1) + m->h.nbf) / 2;
+  out->n_bfacet = m->h.nbf;
   out->n_dof = m->h.E * m->h.dim * m->h.np;
   out->nq_vol = m->t.nq;
   out->nq_facet = m->t.nfq;
@@ -786,8 +806,9 @@ dg_status dg_project(const dg_mesh* m, int n, const double* vals, double* coef_o
   return DG_OK;
 }
 
-dg_status dg_convection_apply(const dg_mesh* m, dg_precision prec, const void* w, const void* u,
-                              void* r, void* stream) {
+namespace {
+dg_status apply_common(const dg_mesh* m, dg_precision prec, const void* w, const void* u,
+                       void* r, void* stream, const Bnd* bc) {
   if (!m || !w || !r) return fail(DG_EINVAL, "null pointer");
   if (!aligned16(w) || !aligned16(r) || (u && !aligned16(u)))
     return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
@@ -798,17 +819,52 @@ dg_status dg_convection_apply(const dg_mesh* m, dg_precision prec, const void* w
   if (st != DG_OK) return st;
   const hipStream_t s = (hipStream_t)stream;
   const int engine = engine_of(m, prec);
-  if (engine >= 0) return run_apply_m(m, engine, w, u, r, s);
+  if (engine >= 0) return run_apply_m(m, engine, w, u, r, s, bc);
   switch (prec) {
-    case DG_FP64: return run_apply<double>(m, w, u, r, s);
-    case DG_FP32: return run_apply<float>(m, w, u, r, s);
+    case DG_FP64: return run_apply<double>(m, w, u, r, s, bc);
+    case DG_FP32: return run_apply<float>(m, w, u, r, s, bc);
     default: return fail(DG_EUNSUPPORTED, "precision not available for dg_convection_apply");
   }
 }
 
+// the outer values a mesh with boundary facets needs: wb always, ub in frozen mode
+dg_status check_bc(const dg_mesh* m, const void* u, const void* wb, const void* ub) {
+  if (m->h.nbf == 0) return DG_OK;
+  if (!wb) return fail(DG_EINVAL, "the mesh has boundary facets: wb is required");
+  if (u && !ub) return fail(DG_EINVAL, "frozen mode on a mesh with boundary facets needs ub");
+  return DG_OK;
+}
+}  // namespace
+
+dg_status dg_convection_apply(const dg_mesh* m, dg_precision prec, const void* w, const void* u,
+                              void* r, void* stream) {
+  if (m && m->h.nbf > 0)
+    return fail(DG_EINVAL, "the mesh has boundary facets: use dg_convection_apply_bc");
+  return apply_common(m, prec, w, u, r, stream, nullptr);
+}
+
+dg_status dg_convection_apply_bc(const dg_mesh* m, dg_precision prec, const void* w,
+                                 const void* u, const void* wb, const void* ub, void* r,
+                                 void* stream) {
+  if (!m) return fail(DG_EINVAL, "null pointer");
+  dg_status st = check_bc(m, u, wb, ub);
+  if (st != DG_OK) return st;
+  const Bnd bc{wb, ub};
+  return apply_common(m, prec, w, u, r, stream, &bc);
+}
+
+dg_status dg_boundary_points(const dg_mesh* m, double* xyz_out) {
+  if (!m || (!xyz_out && m->h.nbf > 0)) return fail(DG_EINVAL, "null pointer");
+  std::vector<double> pts;
+  dgmesh::boundary_points(m->h, pts);
+  if (!pts.empty()) std::memcpy(xyz_out, pts.data(), pts.size() * sizeof(double));
+  return DG_OK;
+}
+
 namespace {
 dg_status rk_common(const dg_mesh* m, dg_precision prec, void* w, double dt, int n,
-                    const void* u, void* work, void* stream, const Extrap* ex) {
+                    const void* u, void* work, void* stream, const Extrap* ex,
+                    const Bnd* bc = nullptr) {
   if (!m || !w) return fail(DG_EINVAL, "null pointer");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be positive and finite");
   if (n < 0) return fail(DG_EINVAL, "n must be >= 0");
@@ -836,21 +892,34 @@ dg_status rk_common(const dg_mesh* m, dg_precision prec, void* w, double dt, int
     work = m->d_work;
   }
   const hipStream_t s = (hipStream_t)stream;
-  if (engine >= 0) return run_rk_m(m, engine, w, dt, n, u, work, s, ex);
-  return prec == DG_FP64 ? run_rk<double>(m, w, dt, n, u, work, s, ex)
-                         : run_rk<float>(m, w, dt, n, u, work, s, ex);
+  if (engine >= 0) return run_rk_m(m, engine, w, dt, n, u, work, s, ex, bc);
+  return prec == DG_FP64 ? run_rk<double>(m, w, dt, n, u, work, s, ex, bc)
+                         : run_rk<float>(m, w, dt, n, u, work, s, ex, bc);
 }
 }  // namespace
 
 dg_status dg_rk_substeps(const dg_mesh* m, dg_precision prec, void* w, double dt, int n,
                          const void* u, void* work, void* stream) {
+  if (m && m->h.nbf > 0)
+    return fail(DG_EINVAL, "the mesh has boundary facets: use dg_rk_substeps_bc");
   return rk_common(m, prec, w, dt, n, u, work, stream, nullptr);
+}
+
+dg_status dg_rk_substeps_bc(const dg_mesh* m, dg_precision prec, void* w, double dt, int n,
+                            const void* u, const void* wb, const void* ub, void* work,
+                            void* stream) {
+  if (!m) return fail(DG_EINVAL, "null pointer");
+  dg_status st = check_bc(m, u, wb, ub);
+  if (st != DG_OK) return st;
+  const Bnd bc{wb, ub};
+  return rk_common(m, prec, w, dt, n, u, work, stream, nullptr, &bc);
 }
 
 dg_status dg_richardson(const dg_mesh* m, dg_precision prec, double* v, const double* g,
                         const double* u, double tau, double ds, double rtol, int max_it,
                         double* work, void* stream, int* iters_out, double* res_out) {
   if (!m || !v || !g || !u) return fail(DG_EINVAL, "null pointer");
+  if (m->h.nbf > 0) return fail(DG_EUNSUPPORTED, "the pseudo-time iteration needs a periodic mesh");
   if (!aligned16(v) || !aligned16(g) || !aligned16(u) || (work && !aligned16(work)))
     return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
   if (g == v || u == v || (work && (work == v || work == g || work == u)))
@@ -884,6 +953,8 @@ dg_status dg_richardson(const dg_mesh* m, dg_precision prec, double* v, const do
 dg_status dg_rk_substeps_extrap(const dg_mesh* m, dg_precision prec, void* w, double dt, int n,
                                 double t0, const void* ua, double ta, const void* ub, double tb,
                                 void* work, void* stream) {
+  if (m && m->h.nbf > 0)
+    return fail(DG_EUNSUPPORTED, "extrapolated-velocity substeps need a periodic mesh");
   if (!ua || !ub) return fail(DG_EINVAL, "null velocity field");
   if (ua == w || ub == w) return fail(DG_EINVAL, "velocity fields must not alias w");
   if (!aligned16(ub)) return fail(DG_EINVAL, "state pointers must be 16-byte aligned");

@@ -142,23 +142,38 @@ int build(int dim, int k, int64_t nvert, const double* xyz, int64_t nelem, const
   double vol = 0;
   for (int64_t t = 0; t < nelem; ++t) vol += H.absdet[t] / (d == 2 ? 2.0 : 6.0);
   H.volume = vol;
-  // periodic matching of centroids via a hash grid
-  double L[3] = {0, 0, 0};
+  // matching of centroids via a hash grid: periodic directions (period > 0) wrap, bounded
+  // directions (period <= 0) do not, and facets left unmatched there are boundary facets
+  double L[3] = {0, 0, 0}, lo[3] = {0, 0, 0};
+  bool wrap[3] = {false, false, false}, any_bounded = false;
+  if (!period) { err = "period is required (entries <= 0 mark bounded directions)"; return -1; }
   for (int j = 0; j < d; ++j) {
-    L[j] = period ? period[j] : 0.0;
-    if (!(L[j] > 0)) { err = "a positive period is required in every direction"; return -1; }
+    wrap[j] = period[j] > 0;
+    any_bounded |= !wrap[j];
+    if (wrap[j]) {
+      L[j] = period[j];
+    } else {
+      double mn = 1e300, mx = -1e300;
+      for (size_t i = 0; i < NFT; ++i) { mn = std::min(mn, cen[i * d + j]); mx = std::max(mx, cen[i * d + j]); }
+      lo[j] = mn;
+      L[j] = (mx - mn) + 4.0 * H.hmin;  // extent of the grid only: never wrapped
+    }
   }
   const double quantum = 1e-3 * H.hmin;
   const double mtol = 1e-7 * H.hmin;
   int64_t ncell[3];
-  for (int j = 0; j < d; ++j) ncell[j] = (int64_t)std::ceil(L[j] / quantum) + 1;
+  for (int j = 0; j < d; ++j) ncell[j] = (int64_t)std::ceil(L[j] / quantum) + 3;
   std::vector<double> wc(NFT * d);
   std::vector<int64_t> cell(NFT * d);
   for (size_t i = 0; i < NFT; ++i)
     for (int j = 0; j < d; ++j) {
       double v = cen[i * d + j];
-      v -= L[j] * std::floor(v / L[j]);
-      if (v > L[j] - 0.5 * quantum) v -= L[j];
+      if (wrap[j]) {
+        v -= L[j] * std::floor(v / L[j]);
+        if (v > L[j] - 0.5 * quantum) v -= L[j];
+      } else {
+        v -= lo[j];
+      }
       wc[i * d + j] = v;
       cell[i * d + j] = (int64_t)std::floor(v / quantum);
     }
@@ -190,7 +205,7 @@ int build(int dim, int k, int64_t nvert, const double* xyz, int64_t nelem, const
         double dist2 = 0;
         for (int j = 0; j < d; ++j) {
           double dd = wc[i * d + j] - wc[o * d + j];
-          dd -= L[j] * std::nearbyint(dd / L[j]);
+          if (wrap[j]) dd -= L[j] * std::nearbyint(dd / L[j]);
           dist2 += dd * dd;
         }
         if (dist2 < mtol * mtol) {
@@ -198,18 +213,30 @@ int build(int dim, int k, int64_t nvert, const double* xyz, int64_t nelem, const
         }
       }
     }
-    if (nfound == 0) { err = "unmatched facet"; return -6; }
     if (nfound > 1) { err = "non-manifold facet"; return -6; }
+    if (nfound == 0) {
+      if (!any_bounded) { err = "unmatched facet"; return -6; }
+      continue;  // a boundary facet, numbered below
+    }
     H.nbr[i] = (int32_t)(found / nf);
     H.nbr_facet[i] = (int32_t)(found % nf);
   }
   for (size_t i = 0; i < NFT; ++i) {
+    if (H.nbr[i] < 0) continue;
     const size_t o = (size_t)H.nbr[i] * nf + H.nbr_facet[i];
     if ((size_t)H.nbr[o] * nf + H.nbr_facet[o] != i) { err = "non-manifold facet"; return -6; }
   }
+  for (size_t i = 0; i < NFT; ++i) {
+    if (H.nbr[i] >= 0) continue;
+    H.nbr[i] = (int32_t)(-1 - H.nbf);
+    H.bf_elem.push_back((int64_t)(i / nf));
+    H.bf_facet.push_back((int32_t)(i % nf));
+    ++H.nbf;
+  }
   H.perm_own = perm;
   H.perm_nbr.resize(NFT);
-  for (size_t i = 0; i < NFT; ++i) H.perm_nbr[i] = perm[(size_t)H.nbr[i] * nf + H.nbr_facet[i]];
+  for (size_t i = 0; i < NFT; ++i)
+    H.perm_nbr[i] = H.nbr[i] < 0 ? 0 : perm[(size_t)H.nbr[i] * nf + H.nbr_facet[i]];
   // element classes: identical (own table, neighbour table) for every local facet
   const int P = n_perm(d);
   std::map<int64_t, int> type_ids;
@@ -220,7 +247,7 @@ int build(int dim, int k, int64_t nvert, const double* xyz, int64_t nelem, const
     for (int f = 0; f < nf; ++f) {
       const size_t i = t * nf + f;
       const int own = f * P + perm[i];
-      const int nb = H.nbr_facet[i] * P + H.perm_nbr[i];
+      const int nb = H.nbr[i] < 0 ? 31 : H.nbr_facet[i] * P + H.perm_nbr[i];
       kk = (kk << 10) | (own << 5) | nb;
     }
     auto it = type_ids.find(kk);
@@ -241,7 +268,7 @@ int build(int dim, int k, int64_t nvert, const double* xyz, int64_t nelem, const
     for (int f = nf - 1; f >= 0; --f) {
       const int nb = (int)(kk & 31), own = (int)((kk >> 5) & 31);
       kk >>= 10;
-      H.type_tab[ty * nf + f] = own | (nb << 16);
+      H.type_tab[ty * nf + f] = own | ((nb == 31 ? kBoundaryTable : nb) << 16);
     }
   }
   build_tiles(H, 64, H.elem_list, H.tile_type, H.ntiles);
@@ -315,6 +342,29 @@ void box_connectivity(int dim, int n, std::vector<double>& xyz, std::vector<int6
           elem.push_back(V(i + e1[0], j + e1[1], l + e1[2]));
           elem.push_back(V(i + 1, j + 1, l + 1));
         }
+}
+
+void boundary_points(const Host& H, std::vector<double>& out) {
+  using dgref::real;
+  const int d = H.dim, nf = d + 1;
+  std::vector<real> fp, fw;
+  dgref::facet_rule<real>(d, dgref::facet_points_1d(H.k), fp, fw);
+  const int nfq = (int)fw.size();
+  out.assign((size_t)H.nbf * nfq * d, 0.0);
+  for (int64_t b = 0; b < H.nbf; ++b) {
+    const int64_t t = H.bf_elem[b];
+    const int f = H.bf_facet[b];
+    int cv[3];
+    canonical_vertices(d, f, H.perm_own[t * nf + f], cv);
+    const double* X = &H.X[(size_t)t * nf * d];
+    for (int q = 0; q < nfq; ++q)
+      for (int j = 0; j < d; ++j) {
+        real x = X[cv[0] * d + j];
+        for (int c = 1; c < d; ++c)
+          x += fp[q * (d - 1) + (c - 1)] * ((real)X[cv[c] * d + j] - (real)X[cv[0] * d + j]);
+        out[((size_t)b * nfq + q) * d + j] = (double)x;
+      }
+  }
 }
 
 void build_tables(int dim, int k, Tables& T) {

@@ -1,6 +1,6 @@
-// Host-side mesh processing: element geometry, periodic facet matching, canonical facet
-// orientation, element classes ("types") with identical facet tables, and the reference
-// tables the kernels read.
+// Host-side mesh processing: element geometry, facet matching (periodic or bounded per box
+// direction), boundary facets, canonical facet orientation, element classes ("types") with
+// identical facet tables, and the reference tables the kernels read.
 #pragma once
 #include <cstdint>
 #include <string>
@@ -14,15 +14,19 @@ struct Host {
   std::vector<double> X;          // [E][d+1][d] unwrapped vertex coordinates
   std::vector<double> jinv;       // [E][d][d]  (J^-1)_{row, col}
   std::vector<double> absdet;     // [E]
-  std::vector<int32_t> nbr;       // [E][d+1]
-  std::vector<int32_t> nbr_facet; // [E][d+1]
+  std::vector<int32_t> nbr;       // [E][d+1]; boundary facet b is encoded as -1 - b
+  std::vector<int32_t> nbr_facet; // [E][d+1]; -1 on boundary facets
+  int64_t nbf = 0;                // boundary facets, numbered in (element, local facet) order
+  std::vector<int64_t> bf_elem;   // [nbf]
+  std::vector<int32_t> bf_facet;  // [nbf]
   std::vector<uint8_t> perm_own;  // [E][d+1] canonical-order permutation code, own side
   std::vector<uint8_t> perm_nbr;  // [E][d+1] same for the neighbour's facet
   double hmin = 0, volume = 0;
   // element classes
   std::vector<int32_t> type_of;   // [E]
   int ntypes = 0;
-  std::vector<int32_t> type_tab;  // [ntypes][d+1]: (own table) | (nbr table << 16)
+  std::vector<int32_t> type_tab;  // [ntypes][d+1]: (own table) | (nbr table << 16); the
+                                  // neighbour table of a boundary facet is kBoundaryTable
   std::vector<int32_t> elem_list; // [ntiles*64], -1 padded (64-wide tiles, VALU kernels)
   std::vector<int32_t> tile_type; // [ntiles], -1 = empty tile
   int ntiles = 0;
@@ -30,6 +34,8 @@ struct Host {
   std::vector<int32_t> tile_type16;
   int ntiles16 = 0;
 };
+
+constexpr int kBoundaryTable = 0x7fff;
 
 void build_tiles(const Host& H, int width, std::vector<int32_t>& elem_list,
                  std::vector<int32_t>& tile_type, int& ntiles);
@@ -39,6 +45,9 @@ int build(int dim, int k, int64_t nvert, const double* xyz, int64_t nelem, const
           const double* period, Host& out, std::string& err);
 
 void box_connectivity(int dim, int n, std::vector<double>& xyz, std::vector<int64_t>& elem);
+
+// physical quadrature points of the boundary facets in canonical order: [nbf][nfq][d]
+void boundary_points(const Host& H, std::vector<double>& out);
 
 // Tables (FP64) for the kernels, concatenated:
 //   Bv [nq][np]            phi_m at the volume points

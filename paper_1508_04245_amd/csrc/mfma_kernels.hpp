@@ -216,6 +216,8 @@ template <typename T>
 struct MArgs {
   const double* x;       // state the operator acts on
   const double* u;       // frozen convecting velocity or nullptr
+  const double* wb;      // outer values at the boundary facet points [nbf][NFQ][D] (or nullptr)
+  const double* ub;      // outer convecting velocity there (frozen mode)
   const double* u2;      // second velocity field or nullptr: u(s) = u + uth (u2 - u)
   const double* w0;      // Runge-Kutta base state (mode 1, a != 0)
   double* out;
@@ -270,7 +272,7 @@ __device__ __forceinline__ typename E::frag vel_frag(const double* p, const doub
 template <int D, int K, bool SELF>
 constexpr int mconv_min_waves() { return dgk::Shape<D, K>::NP >= (SELF ? 35 : 20) ? 1 : (D == 2 && SELF && dgk::Shape<D, K>::NP <= 15 ? 3 : 2); }
 
-template <int D, int K, class E, bool SELF>
+template <int D, int K, class E, bool SELF, bool BND>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mconv_min_waves<D, K, SELF>(), 8)))
 mconv_kernel(MArgs<double> A) {
   using M = MShape<D, K>;
@@ -338,7 +340,10 @@ mconv_kernel(MArgs<double> A) {
   typename E::frag nB[NPF][D][KP], nuB[SELF ? 1 : NPF][SELF ? 1 : D][SELF ? 1 : KP];
   int nce[NPF][D][KP], nue[SELF ? 1 : NPF][SELF ? 1 : D][SELF ? 1 : KP];
   auto load_nbr = [&](int f, int slot) {
-    const int ne = A.nbr[(size_t)e * (D + 1) + f];
+    // a boundary facet has no neighbour: the own element stands in (its traces are replaced
+    // by the boundary data below)
+    const int ne_raw = A.nbr[(size_t)e * (D + 1) + f];
+    const int ne = (BND && ne_raw < 0) ? e : ne_raw;
     const double* pnx = A.x + (size_t)ne * D * NP;
 #pragma unroll
     for (int i = 0; i < D; ++i)
@@ -435,6 +440,8 @@ mconv_kernel(MArgs<double> A) {
     const int nbt = __builtin_amdgcn_readfirstlane(tt >> 16);
     const int slot = NPF > 1 ? f : 0;
     if constexpr (NPF == 1) load_nbr(f, 0);
+    const bool bnd = BND && nbt == dgk::kBoundaryTable;  // uniform: the class fixes it
+    const int nbt_tab = bnd ? own : nbt;  // a valid table for the discarded neighbour product
     double Nt[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -458,12 +465,25 @@ mconv_kernel(MArgs<double> A) {
         for (int kc = 0; kc < KP; ++kc) {
           const int nkc = nk_of(NP - 16 * kc);
           const auto ao = E::load_a(fr, M::OFF_TR + (own * M::FT + ft) * KP + kc, lane, nkc);
-          const auto an = E::load_a(fr, M::OFF_TR + (nbt * M::FT + ft) * KP + kc, lane, nkc);
+          const auto an = E::load_a(fr, M::OFF_TR + (nbt_tab * M::FT + ft) * KP + kc, lane, nkc);
           mma_acc<E>(wm[i], ao, cB[i][kc], ce[i][kc], nkc);
           mma_acc<E>(wp[i], an, nB[slot][i][kc], nce[slot][i][kc], nkc);
           if constexpr (!SELF) {
             mma_acc<E>(um[i], ao, uB[i][kc], ue[i][kc], nkc);
             mma_acc<E>(up[i], an, nuB[slot][i][kc], nue[slot][i][kc], nkc);
+          }
+        }
+      }
+      if (bnd) {
+        // outer values from the boundary data, rows q = 16 ft + row(g, r) of this lane
+        const size_t bf = (size_t)(-1 - A.nbr[(size_t)e * (D + 1) + f]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q = 16 * ft + E::row(g, r);
+#pragma unroll
+          for (int i = 0; i < D; ++i) {
+            wp[i][r] = q < M::NFQ ? (V)A.wb[(bf * M::NFQ + q) * D + i] : V(0);
+            if constexpr (!SELF) up[i][r] = q < M::NFQ ? (V)A.ub[(bf * M::NFQ + q) * D + i] : V(0);
           }
         }
       }

@@ -179,3 +179,46 @@ def test_richardson_argument_errors_before_device_work():
     assert f(m._h, 0, v, g, u, 0.1, 0.5, -1.0, 10, None, None, None, None) == -1
     assert f(m._h, 0, v, g, u, 0.1, 0.5, 1e-6, -1, None, None, None, None) == -1
     assert f(m._h, 1, v, g, u, 0.1, 0.5, 1e-6, 10, None, None, None, None) == -4  # FP32
+
+
+@pytest.mark.parametrize("dim,N,per,jit", [(2, 4, (False, True), 0.2),
+                                           (3, 2, (False, True, False), 0.1)])
+def test_boundary_facets_and_points_match_the_oracle(dim, N, per, jit):
+    """Bounded directions (period <= 0): the library finds the same boundary facets as the
+    oracle, in the same order, and places their quadrature points at the same physical
+    points (the order the outer values are given in)."""
+    from oracle.dg import Space
+    from oracle.mesh import box_mesh
+    om = box_mesh(dim, N, jitter=jit, seed=3, periodic=per)
+    sp = Space(om, 2)
+    E = om.E
+    m = dg.Mesh.from_arrays(dim, 2, om.X.reshape(-1, dim),
+                            np.arange(E * (dim + 1)).reshape(E, dim + 1),
+                            np.where(per, 1.0, 0.0))
+    assert m.info["n_bfacet"] == len(om.bfacets)
+    assert m.info["n_facet"] == (E * (dim + 1) + len(om.bfacets)) // 2
+    nbr, nbf = m.neighbors()
+    bnd = nbr < 0
+    assert np.array_equal(bnd, om.nbr < 0)
+    assert np.array_equal(-1 - nbr[bnd], om.bf_id[bnd])
+    assert np.array_equal(nbr[~bnd], om.nbr[~bnd])
+    assert np.abs(m.boundary_points() - sp.boundary_points()).max() < 1e-14
+
+
+def test_boundary_mesh_needs_the_bc_entry_points():
+    """Errors raised before any device work."""
+    from oracle.mesh import box_mesh
+    om = box_mesh(2, 3, periodic=(False, True))
+    E = om.E
+    m = dg.Mesh.from_arrays(2, 1, om.X.reshape(-1, 2), np.arange(E * 3).reshape(E, 3),
+                            np.array([0.0, 1.0]))
+    L = dg.lib()
+    w, r, u = 4096, 8192, 12288
+    assert L.dg_convection_apply(m._h, 0, w, None, r, None) == -1
+    assert L.dg_rk_substeps(m._h, 0, w, 0.01, 1, None, None, None) == -1
+    assert L.dg_convection_apply_bc(m._h, 0, w, None, None, None, r, None) == -1  # no wb
+    assert L.dg_convection_apply_bc(m._h, 0, w, u, 16384, None, r, None) == -1  # frozen, no ub
+    assert L.dg_rk_substeps_extrap(m._h, 0, w, 0.01, 1, 0.0, u, 0.0, 16384, 1.0, None,
+                                   None) == -4
+    assert L.dg_richardson(m._h, 0, w, 16384, u, 0.1, 0.5, 1e-6, 3, None, None, None,
+                           None) == -4
