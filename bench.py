@@ -98,9 +98,17 @@ def alg_bytes_per_elem(dim, k, esz=8):
     return state * 8.0 / 3.0 + geo
 
 
-def make_state(dg, cfg, seed=0):
+def make_state(dg, cfg, seed=0, mesh="box"):
     from paper_1508_04245_amd import synth
-    m = dg.Mesh.box(cfg["dim"], cfg["n"], cfg["k"])
+    if mesh == "box":
+        m = dg.Mesh.box(cfg["dim"], cfg["n"], cfg["k"])
+    else:
+        # the same box with jittered vertices and, for "shuffled", arbitrary element frames
+        X = synth.box_elements(cfg["dim"], cfg["n"], jitter=0.15, seed=seed + 1,
+                               shuffle=mesh == "shuffled")
+        E, nv, d = X.shape
+        m = dg.Mesh.from_arrays(d, cfg["k"], X.reshape(-1, d), np.arange(E * nv).reshape(E, nv),
+                                np.ones(d))
     n = cfg["k"] + 3
     x = m.project_points(n)
     if cfg["field"] == "tg":
@@ -207,6 +215,9 @@ def main():
     ap.add_argument("--fp64-kernel", default=None, choices=["valu", "mfma"],
                     help="FP64 operator kernel (default: the library's choice)")
     ap.add_argument("--n", type=int, default=None, help="override the mesh size (experiments)")
+    ap.add_argument("--mesh", default="box", choices=["box", "jittered", "shuffled"],
+                    help="jittered: the box with moved vertices; shuffled: also arbitrary "
+                         "element vertex orders (unstructured element frames)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--precision-study", default=None, metavar="CFGS",
@@ -232,7 +243,7 @@ def main():
         cfg["n"] = args.n
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    m, w_host = make_state(dg, cfg)
+    m, w_host = make_state(dg, cfg, mesh=args.mesh)
     ty = torch.float32 if args.precision == "fp32" else torch.float64
     w = torch.tensor(w_host, dtype=ty, device=dev)
     w64 = torch.tensor(w_host, dtype=torch.float64, device=dev)
@@ -272,7 +283,8 @@ def main():
     apply_s = ev0.elapsed_time(ev1) / 1e3 / n_app
     kind, label = kernel_label(cfg, args.precision, args.fp64_kernel)
     tr = MEASURED_TRAFFIC.get((args.config, args.precision, kind))
-    traffic = tr[0] if tr and not args.n and tr[1] == kernel_sources_hash() else None
+    traffic = (tr[0] if tr and not args.n and args.mesh == "box" and tr[1] == kernel_sources_hash()
+               else None)
     out = {
         "metric": "DG convection DOF-updates/s (SSP-RK3 substeps), FP64",
         "value": value,
@@ -292,7 +304,8 @@ def main():
                    if cfg["dim"] == 2 else
                    "3D periodic unit cube %d^3 x6 tets (%d), vector P%d DG, SSP-RK3 dt=%.4g"
                    % (cfg["n"], E, cfg["k"], dt),
-                   "config": args.config, "n_dof": ndof, "precision": args.precision},
+                   "config": args.config, "n_dof": ndof, "precision": args.precision,
+                   "mesh": args.mesh},
         "roofline": {"bound": "alu", "achieved": flops / per_launch / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": flops / per_launch / peak, "traffic": traffic,
                      "traffic_unit": "B/launch", "alg_bytes": byts, "kernel": label,

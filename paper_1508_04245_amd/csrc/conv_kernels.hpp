@@ -55,6 +55,7 @@ struct ConvArgs {
   const int* elem_list;// [ntiles*64], -1 padded
   const int* tile_type;// [ntiles]
   const int* type_tab; // [ntypes][D+1]: own table | nbr table << 16
+  const int* elem_tab; // [E][D+1]: the same per element (per-lane table mode)
   int ntiles;
   int mode;            // 0: r;  1: Runge-Kutta stage;  2: pseudo-time (Richardson) update
   T a, b, dt;
@@ -139,7 +140,17 @@ __device__ __forceinline__ void stage_tables(T* stab, const T* tab) {
 template <int D, int K, typename T>
 constexpr int min_waves() { return Shape<D, K>::NP * D * sizeof(T) <= 15 * 2 * 8 ? 2 : 1; }
 
-template <int D, int K, typename T, bool SELF, int SM, bool BND>
+// LANE: tiles of consecutive elements whatever their classes, each lane reading its own facet
+// tables (from LDS, per-lane addresses; an LDS read returns 8 bytes to each lane either way,
+// so this costs no more LDS bandwidth than a broadcast read), for meshes whose classes would
+// leave class-grouped tiles mostly empty.  Boundary facets are then selected per lane.
+template <int D, int K, typename T>
+constexpr bool lane_tables_ok() {
+  return (size_t)(Shape<D, K>::TOTAL - Shape<D, K>::OFF_TR) * sizeof(T) <= 96 * 1024 &&
+         (size_t)Shape<D, K>::TOTAL * sizeof(T) <= 100 * 1024;
+}
+
+template <int D, int K, typename T, bool SELF, int SM, bool BND, bool LANE = false>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvArgs<T> A) {
   using S = Shape<D, K>;
@@ -247,12 +258,23 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
   // ---- facet terms (pointwise upwind flux)
 #pragma unroll
   for (int f = 0; f <= D; ++f) {
-    const int tt = ttab[type * (D + 1) + f];
-    const int own = __builtin_amdgcn_readfirstlane(tt & 0xffff);
-    const int nbt = __builtin_amdgcn_readfirstlane(tt >> 16);
+    int own, nbt;
+    if constexpr (LANE) {
+      const int tt = A.elem_tab[(size_t)e * (D + 1) + f];
+      own = tt & 0xffff;
+      nbt = tt >> 16;
+    } else {
+      const int tt = ttab[type * (D + 1) + f];
+      own = __builtin_amdgcn_readfirstlane(tt & 0xffff);
+      nbt = __builtin_amdgcn_readfirstlane(tt >> 16);
+    }
     const int tro = S::OFF_TR + own * S::NFQ * NP;
     const int lfo = S::OFF_LF + own * S::NFQ * NP;
-    const int ne = A.nbr[(size_t)e * (D + 1) + f];
+    const int ne_raw = A.nbr[(size_t)e * (D + 1) + f];
+    // per-lane boundary facet (LANE): the own element and table stand in for the neighbour,
+    // and the outer values replace the traces below
+    const bool lbnd = LANE && BND && nbt == kBoundaryTable;
+    const int ne = lbnd ? e : ne_raw;
     T Nt[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -280,11 +302,11 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
         for (int i = 0; i < D; ++i) R[i][m] = fma(-l, F[i], R[i][m]);
       }
     };
-    if (BND && nbt == kBoundaryTable) {
+    if (!LANE && BND && nbt == kBoundaryTable) {
       // boundary facet (the class fixes it for the whole tile; compiled only for meshes that
       // have boundary facets): the outer values are the given boundary data at the facet
       // points, [boundary facet][point][component]
-      const size_t bf = (size_t)(-1 - ne);
+      const size_t bf = (size_t)(-1 - ne_raw);
       const T* __restrict__ pb = A.wb + bf * S::NFQ * D;
       const T* __restrict__ pub = SELF ? pb : A.ub + bf * S::NFQ * D;
 #pragma unroll 1
@@ -311,7 +333,8 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
       }
       continue;
     }
-    const int trn = S::OFF_TR + nbt * S::NFQ * NP;
+    const int trn = S::OFF_TR + (lbnd ? own : nbt) * S::NFQ * NP;
+    const size_t lbf = lbnd ? (size_t)(-1 - ne_raw) : 0;
     T cn[D][NP], un[SELF ? 1 : D][SELF ? 1 : NP];
     {
       const T* __restrict__ p = A.x + (size_t)ne * D * NP;
@@ -363,6 +386,15 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
           for (int i = 0; i < D; ++i) {
             um[i] = fma(to, uc[i][m], um[i]);
             up[i] = fma(tn, un[i][m], up[i]);
+          }
+        }
+      }
+      if constexpr (LANE && BND) {
+        if (lbnd) {
+#pragma unroll
+          for (int i = 0; i < D; ++i) {
+            wp[i] = A.wb[(lbf * S::NFQ + q) * D + i];
+            up[i] = SELF ? wp[i] : A.ub[(lbf * S::NFQ + q) * D + i];
           }
         }
       }

@@ -162,9 +162,17 @@ constexpr int default_tab_src() {
   return 0;
 }
 
-template <int D, int K, typename T, bool SELF, int SM, bool BND = false>
+template <int D, int K, typename T, bool SELF, int SM, bool BND = false, bool LANE = false>
 void launch_conv_sm(const dgk::ConvArgs<T>& a, dim3 grid, hipStream_t s) {
-  hipLaunchKernelGGL((dgk::conv_kernel<D, K, T, SELF, SM, BND>), grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL((dgk::conv_kernel<D, K, T, SELF, SM, BND, LANE>), grid, dim3(256), 0, s, a);
+}
+
+// per-lane table mode: the facet tables must come from LDS; the volume tables go through
+// scalar loads when the whole set does not fit the 64 KiB a class-tiled kernel stages
+template <int D, int K, typename T>
+constexpr int lane_tab_src() {
+  return (size_t)dgk::Shape<D, K>::TOTAL * sizeof(T) <= 65536 ? 0
+                                                              : (1 << dgk::TB_BV) | (1 << dgk::TB_DV);
 }
 
 template <int D, int K, typename T, bool SELF>
@@ -175,12 +183,19 @@ hipError_t launch_conv_dk(const dg_mesh* m, const dgk::ConvArgs<T>& a, hipStream
     return hipErrorInvalidValue;
   if ((int64_t)m->h.elem_list.size() != (int64_t)m->h.ntiles * 64) return hipErrorInvalidValue;
   const dim3 grid((m->h.ntiles + 3) / 4);
-  // DGCONV_TABLES may pick another split for the FP64 self kernel: every table in LDS (0),
-  // every table through scalar loads (31), or the 2D P4 default (21)
+  if (m->h.lane_tables) {
+    if constexpr (dgk::lane_tables_ok<D, K, T>()) {
+      launch_conv_sm<D, K, T, SELF, lane_tab_src<D, K, T>(), true, true>(a, grid, s);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;  // never chosen at mesh creation for such elements
+  }
   if (m->h.nbf > 0) {  // meshes with boundary facets: the variant that handles them
     launch_conv_sm<D, K, T, SELF, kDef, true>(a, grid, s);
     return hipGetLastError();
   }
+  // DGCONV_TABLES may pick another split for the FP64 self kernel: every table in LDS (0),
+  // every table through scalar loads (31), or the 2D P4 default (21)
   const int src = m->tab_src < 0 || !dgk::tables_in_lds<D, K, T>() ? kDef : m->tab_src;
   if constexpr (dgk::tables_in_lds<D, K, T>() && SELF && sizeof(T) == 8) {
     if (src != kDef) {
@@ -228,6 +243,7 @@ dgk::ConvArgs<T> base_args(const dg_mesh* m) {
   a.elem_list = m->d_elem_list;
   a.tile_type = m->d_tile_type;
   a.type_tab = m->d_type_tab;
+  a.elem_tab = m->d_elem_tab;
   a.ntiles = m->h.ntiles;
   return a;
 }
@@ -640,6 +656,7 @@ dg_status dgi::ensure_device(const dg_mesh* cm) {
       (s = upload(m->h.type_tab, &m->d_type_tab)) != DG_OK ||
       (s = upload(m->h.elem_list16, &m->d_elem_list16)) != DG_OK ||
       (s = upload(m->h.tile_type16, &m->d_tile_type16)) != DG_OK ||
+      (!m->h.elem_tab.empty() && (s = upload(m->h.elem_tab, &m->d_elem_tab)) != DG_OK) ||
       (s = upload(zeros, &m->d_partial)) != DG_OK)
     return s;
   {
@@ -660,7 +677,8 @@ using dgi::ensure_device;
 void free_mesh(dg_mesh* m) {
   if (!m) return;
   void* ptrs[] = {m->d_tab, m->d_tab_f, m->d_jinv, m->d_jinv_f, m->d_absdet, m->d_nbr,
-                  m->d_elem_list, m->d_tile_type, m->d_type_tab, m->d_work, m->d_partial,
+                  m->d_elem_list, m->d_tile_type, m->d_type_tab, m->d_elem_tab, m->d_work,
+                  m->d_partial,
                   m->d_rich_partial, m->d_rich_state, m->d_elem_list16, m->d_tile_type16, m->d_frag[0], m->d_frag[1], m->d_frag[2]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -701,8 +719,17 @@ dg_status dg_mesh_create(int dim, int k, int64_t n_vert, const double* xyz, int6
     // 3D P3 1360 / 575, 2D P3 15.5 / 13.5, 2D P4 49 / 54, 3D P2 809 / 1005.  Matrix cores
     // for elements with >= 20 basis functions and for 2D P3, the VALU kernel otherwise;
     // DGCONV_FP64_KERNEL=valu|mfma overrides
+    // Per-lane facet tables (64-wide tiles in element order) when the element classes would
+    // leave the class-grouped tiles less than 3/4 full, as on meshes with arbitrary vertex
+    // orders, and the facet tables fit in LDS; DGCONV_LANE_TABLES=0|1 overrides
+    const double fill = (double)n_elem / (64.0 * std::max(1, m->h.ntiles));
+    const bool lane_ok = (m->t.total - m->t.off_tr) * 8 <= 96 * 1024 && m->t.total * 8 <= 100 * 1024;
+    const char* lt = std::getenv("DGCONV_LANE_TABLES");
+    const bool lane = lane_ok && (lt ? std::string(lt) == "1" : fill < 0.75);
+    if (lane) dgmesh::use_lane_tables(m->h);
     const char* fk = std::getenv("DGCONV_FP64_KERNEL");
-    m->fp64_mfma = fk ? std::string(fk) == "mfma" : (m->h.np >= 20 || (dim == 2 && k == 3));
+    m->fp64_mfma = fk ? std::string(fk) == "mfma"
+                      : (m->h.np >= 20 || (dim == 2 && k == 3)) && !lane;
   }
   *out = m;
   return DG_OK;

@@ -37,6 +37,7 @@ struct dg_mesh {
   int* d_elem_list = nullptr;
   int* d_tile_type = nullptr;
   int* d_type_tab = nullptr;
+  int* d_elem_tab = nullptr;  // per-element facet tables (per-lane table mode)
   mutable void* d_work = nullptr;
   mutable size_t work_bytes = 0;
   double* d_partial = nullptr;  // reduction partials

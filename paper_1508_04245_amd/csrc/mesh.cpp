@@ -281,14 +281,14 @@ int build(int dim, int k, int64_t nvert, const double* xyz, int64_t nelem, const
 // tiles, and the block's tile count is padded to a multiple of 4 with empty tiles (class -1),
 // so every tile of a workgroup covers the same contiguous range of the state arrays.
 void build_tiles(const Host& H, int width, std::vector<int32_t>& elem_list,
-                 std::vector<int32_t>& tile_type, int& ntiles) {
+                 std::vector<int32_t>& tile_type, int& ntiles, bool by_class) {
   elem_list.clear();
   tile_type.clear();
   const int64_t bsz = 4 * width;
   for (int64_t b0 = 0; b0 < H.E; b0 += bsz) {
     const int64_t b1 = std::min<int64_t>(H.E, b0 + bsz);
     std::map<int, std::vector<int32_t>> by_type;
-    for (int64_t t = b0; t < b1; ++t) by_type[H.type_of[t]].push_back((int32_t)t);
+    for (int64_t t = b0; t < b1; ++t) by_type[by_class ? H.type_of[t] : 0].push_back((int32_t)t);
     int ntile_block = 0;
     for (auto& kv : by_type) {
       const auto& mm = kv.second;
@@ -306,6 +306,15 @@ void build_tiles(const Host& H, int width, std::vector<int32_t>& elem_list,
     }
   }
   ntiles = (int)tile_type.size();
+}
+
+void use_lane_tables(Host& H) {
+  const int nf = H.dim + 1;
+  H.elem_tab.resize((size_t)H.E * nf);
+  for (int64_t t = 0; t < H.E; ++t)
+    for (int f = 0; f < nf; ++f) H.elem_tab[t * nf + f] = H.type_tab[(size_t)H.type_of[t] * nf + f];
+  build_tiles(H, 64, H.elem_list, H.tile_type, H.ntiles, false);
+  H.lane_tables = true;
 }
 
 void box_connectivity(int dim, int n, std::vector<double>& xyz, std::vector<int64_t>& elem) {

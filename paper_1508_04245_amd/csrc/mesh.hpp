@@ -27,6 +27,8 @@ struct Host {
   int ntypes = 0;
   std::vector<int32_t> type_tab;  // [ntypes][d+1]: (own table) | (nbr table << 16); the
                                   // neighbour table of a boundary facet is kBoundaryTable
+  std::vector<int32_t> elem_tab;  // [E][d+1]: type_tab of each element's class (per-lane mode)
+  bool lane_tables = false;       // 64-wide tiles in element order, facet tables per lane
   std::vector<int32_t> elem_list; // [ntiles*64], -1 padded (64-wide tiles, VALU kernels)
   std::vector<int32_t> tile_type; // [ntiles], -1 = empty tile
   int ntiles = 0;
@@ -38,7 +40,11 @@ struct Host {
 constexpr int kBoundaryTable = 0x7fff;
 
 void build_tiles(const Host& H, int width, std::vector<int32_t>& elem_list,
-                 std::vector<int32_t>& tile_type, int& ntiles);
+                 std::vector<int32_t>& tile_type, int& ntiles, bool by_class = true);
+
+// switch the 64-wide tiles to element order with per-lane facet tables (for meshes whose
+// element classes leave the class-grouped tiles mostly empty)
+void use_lane_tables(Host& H);
 
 // returns empty string on success, else an error message; code set to a dg_status value
 int build(int dim, int k, int64_t nvert, const double* xyz, int64_t nelem, const int64_t* elem,

@@ -71,3 +71,35 @@ def shear_wave(x, t, c, xi, eta, A=1.0):
 def noise(shape, seed=0, sd=1e-3):
     """Seeded Gaussian noise on the coefficients."""
     return np.random.default_rng(seed).normal(0.0, sd, size=shape)
+
+
+def box_elements(dim, N, jitter=0.0, seed=0, shuffle=False):
+    """Per-element vertex coordinates [E, dim+1, dim] of the periodic unit box cut into N^dim
+    cells, 2 triangles (lower (v00, v10, v11), upper (v11, v01, v00)) or 6 Kuhn tetrahedra
+    (v000, v000+e_s0, v000+e_s0+e_s1, v111) per cell, cells in x-fastest order.  `jitter` > 0
+    moves every lattice vertex by a seeded periodic offset of that size times 1/N (copies of
+    a vertex move together); `shuffle` permutes each element's vertex order at random (seeded),
+    the same mesh with arbitrary element frames.  Input geometry only."""
+    import itertools
+    rng = np.random.default_rng(seed)
+    h = 1.0 / N
+    off = rng.uniform(-1, 1, size=(N,) * dim + (dim,)) * jitter * h if jitter else None
+    if dim == 2:
+        j, i = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+        b = np.stack([i.ravel(), j.ravel()], axis=1)
+        lat = np.stack([np.stack([b, b + [1, 0], b + [1, 1]], 1),
+                        np.stack([b + [1, 1], b + [0, 1], b], 1)], axis=1).reshape(-1, 3, 2)
+    else:
+        l, j, i = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+        b = np.stack([i.ravel(), j.ravel(), l.ravel()], axis=1)
+        eye = np.eye(3, dtype=np.int64)
+        lat = np.stack([np.stack([b, b + eye[s[0]], b + eye[s[0]] + eye[s[1]], b + 1], 1)
+                        for s in itertools.permutations(range(3))], axis=1).reshape(-1, 4, 3)
+    X = lat * h
+    if off is not None:
+        w = np.mod(lat, N)
+        X = X + off[tuple(w[..., a] for a in range(dim))]
+    if shuffle:
+        perm = np.argsort(rng.random((X.shape[0], dim + 1)), axis=1)
+        X = np.take_along_axis(X, perm[:, :, None], axis=1)
+    return X

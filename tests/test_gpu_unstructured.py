@@ -1,0 +1,85 @@
+"""GPU parity on meshes with arbitrary element frames (each element's vertex order shuffled,
+so neighbouring facets meet in every orientation and the element classes number in the
+hundreds): the per-lane facet-table mode (tiles in element order) and the class-tiled mode
+against the oracle, periodic and with boundary facets.  Every test prints its case first.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_common import initial_state, rel_l2, say
+from oracle.dg import Space, cfl_dt
+from oracle.mesh import Mesh, box_mesh
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import paper_1508_04245_amd as dg
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    dg.lib()
+    return dg
+
+
+def dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def shuffled(dim, N, periodic, seed):
+    base = box_mesh(dim, N, jitter=0.15, seed=seed, periodic=periodic)
+    rng = np.random.default_rng(seed)
+    X = base.X.copy()
+    for t in range(base.E):
+        X[t] = X[t][rng.permutation(dim + 1)]
+    return Mesh(X, base.period)
+
+
+CASES = [(2, 2, 9, (True, True)), (2, 4, 6, (True, True)), (3, 2, 3, (True, True, True)),
+         (2, 3, 7, (False, True)), (3, 2, 3, (False, True, True))]
+
+
+@pytest.mark.parametrize("dim,k,N,per", CASES)
+def test_shuffled_frames_vs_oracle(dg, dim, k, N, per):
+    say("case shuffled dim=%d k=%d N=%d periodic=%s" % (dim, k, N, per))
+    om = shuffled(dim, N, per, seed=7)
+    sp = Space(om, k)
+    w = initial_state(sp, seed=1, sd=0.05)
+    u = 0.5 * initial_state(sp, field="fourier", seed=2)
+    bounded = not all(per)
+    if bounded:
+        xb = sp.boundary_points()
+        wb = np.sin(2 * np.pi * xb) * 0.3 + 0.5
+        ub = 0.5 * wb
+    else:
+        wb = ub = None
+    ref_self = sp.apply(w, wb=wb)
+    ref_frozen = sp.apply(w, u, wb=wb, ub=ub)
+    dt = cfl_dt(1.0 / N, k, sp.max_speed(w))
+    ref_rk = sp.ssprk3(w, dt, 2, wb=wb)
+    E = om.E
+    for lane in ("1", "0"):
+        os.environ["DGCONV_LANE_TABLES"] = lane
+        for prec in ("fp64", "fp32"):
+            say("   lane tables %s, %s" % (lane, prec))
+            m = dg.Mesh.from_arrays(dim, k, om.X.reshape(-1, dim),
+                                    np.arange(E * (dim + 1)).reshape(E, dim + 1), om.period)
+            ty = torch.float32 if prec == "fp32" else torch.float64
+            W = dev(w, ty)
+            if bounded:
+                r1 = m.apply_bc(W, dev(wb, ty), precision=prec)
+                r2 = m.apply_bc(W, dev(wb, ty), u=dev(u, ty), ub=dev(ub, ty), precision=prec)
+                m.rk_substeps_bc(W, dt, 2, dev(wb, ty), precision=prec)
+            else:
+                r1 = m.apply(W, precision=prec)
+                r2 = m.apply(W, dev(u, ty), precision=prec)
+                m.rk_substeps(W, dt, 2, precision=prec)
+            e = [rel_l2(sp, r1.double().cpu().numpy(), ref_self),
+                 rel_l2(sp, r2.double().cpu().numpy(), ref_frozen),
+                 rel_l2(sp, W.double().cpu().numpy(), ref_rk)]
+            say("      self %.3e  frozen %.3e  substeps %.3e" % tuple(e))
+            tol = 1e-12 if prec == "fp64" else 1e-4
+            assert max(e) <= tol, (lane, prec, e)
+    os.environ.pop("DGCONV_LANE_TABLES", None)
