@@ -58,6 +58,10 @@ def lib():
         "dg_rk_substeps": [P, I, P, D, I, P, P, P],
         "dg_rk_substeps_extrap": [P, I, P, D, I, D, P, D, P, D, P, P],
         "dg_boundary_points": [P, P],
+        "dg_hdiv_info": [P, P, P],
+        "dg_hdiv_reference": [I, P],
+        "dg_transfer_to_dg": [P, P, P, P],
+        "dg_transfer_transpose": [P, P, P, P],
         "dg_convection_apply_bc": [P, I, P, P, P, P, P, P],
         "dg_rk_substeps_bc": [P, I, P, D, I, P, P, P, P, P],
         "dg_richardson": [P, I, P, P, P, D, D, D, I, P, P, P, P],
@@ -187,7 +191,31 @@ class Mesh:
         _check(lib().dg_boundary_points(self._h, _ptr(out) if nb else None))
         return out
 
+    def hdiv_size(self):
+        """(dim W_h, number of facets) of the H(div) space (2D, k >= 1)."""
+        n, nf = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib().dg_hdiv_info(self._h, ctypes.byref(n), ctypes.byref(nf)))
+        return n.value, nf.value
+
     # ---- device calls
+    def to_dg(self, u, out=None, stream=None):
+        """I u: DG coefficients of the W_h field with coefficients u (dev [n_dof])."""
+        import torch
+        if out is None:
+            out = torch.empty((self.E, self.dim, self.np), dtype=torch.float64, device=u.device)
+        _check(lib().dg_transfer_to_dg(self._h, _dev(u, torch.float64), _dev(out, torch.float64),
+                                       _stream(stream)))
+        return out
+
+    def transfer_transpose(self, f, out=None, stream=None):
+        """I^T f for a functional f given by its values on the DG basis (dev state)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.hdiv_size()[0], dtype=torch.float64, device=f.device)
+        _check(lib().dg_transfer_transpose(self._h, _dev(f, torch.float64),
+                                           _dev(out, torch.float64), _stream(stream)))
+        return out
+
     def apply(self, w, u=None, out=None, precision="fp64", stream=None):
         """r = -(M^V)^-1 C^V(u) w on the device (u=None: self-convection)."""
         import torch

@@ -32,7 +32,8 @@ def build(verbose=True):
     """Compile every HIP source for gfx950 and link libdgconv.so (always rebuilds)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []
-    srcs = [("dgconv.hip", True), ("surrogate.hip", True), ("mesh.cpp", False)]
+    srcs = [("dgconv.hip", True), ("surrogate.hip", True), ("transfer.hip", True),
+            ("mesh.cpp", False), ("hdiv.cpp", False)]
     tmpdir = os.path.join(HERE, "_build")
     os.makedirs(tmpdir, exist_ok=True)
     procs = []

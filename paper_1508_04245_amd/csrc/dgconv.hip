@@ -678,8 +678,9 @@ void free_mesh(dg_mesh* m) {
   if (!m) return;
   void* ptrs[] = {m->d_tab, m->d_tab_f, m->d_jinv, m->d_jinv_f, m->d_absdet, m->d_nbr,
                   m->d_elem_list, m->d_tile_type, m->d_type_tab, m->d_elem_tab, m->d_work,
-                  m->d_partial,
-                  m->d_rich_partial, m->d_rich_state, m->d_elem_list16, m->d_tile_type16, m->d_frag[0], m->d_frag[1], m->d_frag[2]};
+                  m->d_partial, m->d_rich_partial, m->d_rich_state, m->d_elem_list16,
+                  m->d_tile_type16, m->d_frag[0], m->d_frag[1], m->d_frag[2], m->d_hfacet,
+                  m->d_hfelem, m->d_htab, m->d_hlocal};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "../../include/dgconv.h"
+#include "hdiv.hpp"
 #include "mesh.hpp"
 
 namespace dgi {
@@ -51,6 +52,13 @@ struct dg_mesh {
   int* d_elem_list16 = nullptr;
   int* d_tile_type16 = nullptr;
   void* d_frag[3] = {nullptr, nullptr, nullptr};  // 0: f64, 1: fp16 x2, 2: bf16 x3
+  // H(div) transfer (2D): numbering and tables built on first use
+  bool hd_ready = false;
+  dghdiv::Host hd;
+  int* d_hfacet = nullptr;          // [E][3] facet id and signs
+  int64_t* d_hfelem = nullptr;      // [nfacet][2] sides of each facet
+  double* d_htab = nullptr;         // [ndof][2][np] reference dual basis
+  double* d_hlocal = nullptr;       // [E][ndof] element contributions of the transpose
   std::mutex mu;
 };
 

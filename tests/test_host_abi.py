@@ -222,3 +222,32 @@ def test_boundary_mesh_needs_the_bc_entry_points():
                                    None) == -4
     assert L.dg_richardson(m._h, 0, w, 16384, u, 0.1, 0.5, 1e-6, 3, None, None, None,
                            None) == -4
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 6])
+def test_hdiv_reference_basis_matches_the_oracle(k):
+    """The library's reference dual basis (long double Gauss-Jordan of its own moment matrix)
+    equals the oracle's (NumPy inverse), dof by dof."""
+    from oracle.hdiv import reference_dual
+    nb = (k + 1) * (k + 2) // 2
+    tab = np.zeros(((k + 1) * (k + 2), 2, nb))
+    assert dg.lib().dg_hdiv_reference(k, dg._ptr(tab)) == 0
+    C = reference_dual(k)  # [(a, m), j]
+    ref = C.T.reshape(-1, 2, nb)
+    assert np.abs(tab - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+def test_hdiv_size_matches_the_oracle():
+    from oracle.hdiv import HdivSpace
+    from oracle.mesh import box_mesh
+    for per in [(True, True), (False, True)]:
+        om = box_mesh(2, 4, jitter=0.1, seed=2, periodic=per)
+        E = om.E
+        m = dg.Mesh.from_arrays(2, 3, om.X.reshape(-1, 2), np.arange(E * 3).reshape(E, 3),
+                                np.where(per, 1.0, 0.0))
+        H = HdivSpace(om, 3)
+        assert m.hdiv_size() == (H.N, H.n_facets)
+    m3 = dg.Mesh.box(3, 2, 2)
+    with pytest.raises(dg.DGError) as e:
+        m3.hdiv_size()
+    assert e.value.status == -4
