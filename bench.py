@@ -31,7 +31,8 @@ TRAFFIC_SOURCES = ("paper_1508_04245_amd/csrc/conv_kernels.hpp",
                    "paper_1508_04245_amd/csrc/mfma_kernels.hpp",
                    "paper_1508_04245_amd/csrc/dgconv.hip")
 MEASURED_TRAFFIC = {
-    ("c2", "fp64", "valu"): (109.6e6, "1edadeabe8b21c03"),
+    ("c2", "fp64", "valu"): (110.9e6, "3cfdcbd2535df630"),
+    ("c3", "fp64", "mfma"): (428.5e6, "3cfdcbd2535df630"),
 }
 
 
@@ -205,6 +206,81 @@ def precision_study(dg, cfgs, tol=1e-6):
                           "best_within_tol": best}), flush=True)
 
 
+def rows_study(dg, reps=50):
+    """Timing of the rows beside the self-convection substeps, on the 2D 256x256x2 P4 mesh
+    (FP64, inputs resident): frozen-velocity substeps, substeps with the velocity extrapolated
+    in time, the pseudo-time (Richardson) update, substeps on the bounded channel, and the
+    H(div) <-> DG transfers.  One JSON line per row, with its HBM-byte equivalent (algorithmic
+    bytes: state reads and writes, neighbour states counted once, geometry)."""
+    import torch
+    from paper_1508_04245_amd import synth
+    dev = torch.device("cuda", 0)
+    cfg = CONFIGS["c2"]
+    m, wh = make_state(dg, cfg)
+    w = torch.tensor(wh, device=dev)
+    u = torch.tensor(0.5 * wh, device=dev)
+    u2 = torch.tensor(0.6 * wh, device=dev)
+    E, ndof = m.info["n_elem"], m.info["n_dof"]
+    st = ndof * 8
+    geo = E * 48
+    dt = 0.1 / cfg["n"] / (cfg["k"] ** 2 * float(m.reduce("maxvel", w)[0].item()))
+    work = torch.empty((2,) + tuple(w.shape), dtype=torch.float64, device=dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(n):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / 1e3 / n
+
+    def emit(row, sec, launches, byts, extra=None):
+        out = {"row": row, "workload": "2D periodic 256x256x2 triangles, P4, FP64",
+               "s_per_call": sec, "us_per_launch": sec / launches * 1e6,
+               "hbm_equiv_GBps": byts / (sec / launches) / 1e9}
+        out.update(extra or {})
+        print(json.dumps(out), flush=True)
+
+    t = timed(lambda: m.rk_substeps(w, dt, 1, u=u, work=work), reps)
+    emit("frozen-velocity SSP-RK3 substep", t, 3, st * (8.0 / 3 + 1) + geo,
+         {"dof_updates_per_s": ndof / t})
+    t = timed(lambda: m.rk_substeps_extrap(w, dt, 1, 0.0, u, -dt, u2, 0.0, work=work), reps)
+    emit("extrapolated-velocity SSP-RK3 substep", t, 3, st * (8.0 / 3 + 2) + geo,
+         {"dof_updates_per_s": ndof / t})
+    g = w.clone()
+    v = w.clone()
+    h = 1.0 / cfg["n"]
+    tau = 0.5 * h
+    ds = 1.0 / (1.0 + tau * 25 / h)
+    n_it = 40
+    t = timed(lambda: m.richardson(v.copy_(g), g, u, tau, ds, 0.0, n_it, work=work), 5)
+    emit("pseudo-time (Richardson) update", t, n_it, st * 4 + geo,
+         {"updates_per_s": n_it / t, "updates_per_call": n_it})
+    # bounded channel of the same size: x bounded, inflow data on its two sides
+    X = synth.box_elements(2, cfg["n"])
+    mc = dg.Mesh.from_arrays(2, cfg["k"], X.reshape(-1, 2), np.arange(X.shape[0] * 3).reshape(-1, 3),
+                             np.array([0.0, 1.0]))
+    xb = mc.boundary_points()
+    wb = torch.tensor(np.stack([np.ones(xb.shape[:2]), 0.5 * np.sin(2 * np.pi * xb[..., 1])], -1),
+                      device=dev)
+    wc = w.clone()
+    t = timed(lambda: mc.rk_substeps_bc(wc, dt, 1, wb, work=work), reps)
+    emit("bounded-channel SSP-RK3 substep", t, 3, st * 8.0 / 3 + geo,
+         {"dof_updates_per_s": ndof / t, "n_bfacet": mc.info["n_bfacet"]})
+    n_w, n_f = m.hdiv_size()
+    uh = torch.randn(n_w, dtype=torch.float64, device=dev)
+    out = torch.empty_like(w)
+    t = timed(lambda: m.to_dg(uh, out=out), reps)
+    emit("transfer I (W_h -> V_h)", t, 1, n_w * 8 + st + E * 44, {"n_hdiv": n_w})
+    gt = torch.empty(n_w, dtype=torch.float64, device=dev)
+    t = timed(lambda: m.transfer_transpose(w, out=gt), reps)
+    emit("transfer I^T (V_h' -> W_h')", t, 2, st + 2 * E * 2 * m.np * 8 + n_w * 8 + E * 44,
+         {"n_hdiv": n_w})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +296,8 @@ def main():
                          "element vertex orders (unstructured element frames)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
+    ap.add_argument("--rows", action="store_true",
+                    help="time the rows beside the self-convection substeps (one JSON line each)")
     ap.add_argument("--precision-study", default=None, metavar="CFGS",
                     help="comma-separated configs: final-state error and speedup of every "
                          "precision variant against FP64 (one JSON line per config)")
@@ -237,6 +315,9 @@ def main():
     dg.lib()
     if args.precision_study:
         precision_study(dg, args.precision_study.split(","))
+        return
+    if args.rows:
+        rows_study(dg)
         return
     cfg = dict(CONFIGS[args.config])
     if args.n:
