@@ -454,10 +454,10 @@ dgm::MArgs<double> mbase_args(const dg_mesh* m, int engine) {
 }
 
 // engine of a precision on the matrix-core path, or -1 for the VALU kernels
-int engine_of(const dg_mesh* m, dg_precision prec) {
+int engine_of(const dg_mesh* m, dg_precision prec, bool frozen) {
   if (prec == DG_MIX_F16x2) return 1;
   if (prec == DG_MIX_BF16x3) return 2;
-  if (prec == DG_FP64 && m->fp64_mfma) return 0;
+  if (prec == DG_FP64 && (frozen ? m->fp64_mfma_frozen : m->fp64_mfma)) return 0;
   return -1;
 }
 
@@ -728,9 +728,13 @@ dg_status dg_mesh_create(int dim, int k, int64_t n_vert, const double* xyz, int6
     const char* lt = std::getenv("DGCONV_LANE_TABLES");
     const bool lane = lane_ok && (lt ? std::string(lt) == "1" : fill < 0.75);
     if (lane) dgmesh::use_lane_tables(m->h);
+    // With a given velocity field (frozen or extrapolated) the VALU kernel holds a second
+    // set of coefficients and spills from 10 basis functions on (2D P4: 228 us against 84 us
+    // per launch on the matrix cores), so that mode takes the matrix cores from there.
     const char* fk = std::getenv("DGCONV_FP64_KERNEL");
     m->fp64_mfma = fk ? std::string(fk) == "mfma"
                       : (m->h.np >= 20 || (dim == 2 && k == 3)) && !lane;
+    m->fp64_mfma_frozen = fk ? std::string(fk) == "mfma" : m->h.np >= 10 && !lane;
   }
   *out = m;
   return DG_OK;
@@ -846,7 +850,7 @@ dg_status apply_common(const dg_mesh* m, dg_precision prec, const void* w, const
   dg_status st = ensure_device(m);
   if (st != DG_OK) return st;
   const hipStream_t s = (hipStream_t)stream;
-  const int engine = engine_of(m, prec);
+  const int engine = engine_of(m, prec, u != nullptr);
   if (engine >= 0) return run_apply_m(m, engine, w, u, r, s, bc);
   switch (prec) {
     case DG_FP64: return run_apply<double>(m, w, u, r, s, bc);
@@ -903,7 +907,7 @@ dg_status rk_common(const dg_mesh* m, dg_precision prec, void* w, double dt, int
     return fail(DG_EINVAL, "unknown precision");
   dg_status st = ensure_device(m);
   if (st != DG_OK) return st;
-  const int engine = engine_of(m, prec);
+  const int engine = engine_of(m, prec, u != nullptr);
   if (engine >= 0 && (st = ensure_frags(m, engine)) != DG_OK) return st;
   if (!work) {
     // the mesh-owned work buffer (2 states), grown on demand
@@ -960,7 +964,7 @@ dg_status dg_richardson(const dg_mesh* m, dg_precision prec, double* v, const do
     return fail(DG_EINVAL, "unknown precision");
   dg_status st = ensure_device(m);
   if (st != DG_OK) return st;
-  const int engine = engine_of(m, prec);
+  const int engine = engine_of(m, prec, u != nullptr);
   if (engine >= 0 && (st = ensure_frags(m, engine)) != DG_OK) return st;
   if (!work) {
     std::lock_guard<std::mutex> lock(const_cast<dg_mesh*>(m)->mu);
