@@ -368,13 +368,18 @@ mconv_kernel(MArgs<double> A) {
   for (int a = 0; a < D; ++a)
 #pragma unroll
     for (int j = 0; j < D; ++j) ji_v[a][j] = (V)ji[a][j];
-  V Rv[D][KP][4];
+  // 2D: one accumulator set per gradient direction a, so the test contraction runs 2 D
+  // independent MFMA chains instead of D (summed after the loop)
+  constexpr int NA = D == 2 ? D : 1;
+  V Rv[NA][D][KP][4];
 #pragma unroll
-  for (int i = 0; i < D; ++i)
+  for (int b = 0; b < NA; ++b)
 #pragma unroll
-    for (int mt = 0; mt < KP; ++mt)
+    for (int i = 0; i < D; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Rv[i][mt][r] = V(0);
+      for (int mt = 0; mt < KP; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Rv[b][i][mt][r] = V(0);
 #pragma unroll(M::QT <= 4 ? M::QT : 1)
   for (int qt = 0; qt < M::QT; ++qt) {
     V W[D][4], U[SELF ? 1 : D][4];
@@ -421,7 +426,7 @@ mconv_kernel(MArgs<double> A) {
         const int nkq = nk_of(M::NQ - 16 * qt);
         const auto af = E::load_a(fr, M::OFF_DV + (a * KP + mt) * M::QT + qt, lane, nkq);
 #pragma unroll
-        for (int i = 0; i < D; ++i) mma_acc<E>(Rv[i][mt], af, gB[i], ge[i], nkq);
+        for (int i = 0; i < D; ++i) mma_acc<E>(Rv[NA > 1 ? a : 0][i][mt], af, gB[i], ge[i], nkq);
       }
     }
   }
@@ -430,7 +435,12 @@ mconv_kernel(MArgs<double> A) {
 #pragma unroll
     for (int mt = 0; mt < KP; ++mt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) R[i][mt][r] = (double)Rv[i][mt][r];
+      for (int r = 0; r < 4; ++r) {
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < NA; ++b) acc += (double)Rv[b][i][mt][r];
+        R[i][mt][r] = acc;
+      }
 
   // ---------------- facets
 #pragma unroll(D == 2 ? D + 1 : 1)
