@@ -1,0 +1,67 @@
+"""GPU edge cases against the oracle: the smallest periodic meshes (one cell: 2 triangles or
+6 tetrahedra, every facet matched across the period), zero substeps, the zero state, and a
+mesh smaller than one tile for every kernel family.  Every test prints its case first.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_common import initial_state, rel_l2, say
+from oracle.dg import Space, cfl_dt
+from oracle.mesh import box_mesh
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import paper_1508_04245_amd as dg
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    dg.lib()
+    return dg
+
+
+def dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+@pytest.mark.parametrize("dim,k", [(2, 0), (2, 2), (2, 4), (3, 1), (3, 3)])
+def test_one_cell_meshes(dg, dim, k):
+    say("case one cell dim=%d k=%d" % (dim, k))
+    sp = Space(box_mesh(dim, 1), k)
+    w = initial_state(sp, seed=3, sd=0.1)
+    u = initial_state(sp, field="fourier", seed=4)
+    for kern, prec, tol in [("valu", "fp64", 1e-12), ("mfma", "fp64", 1e-12),
+                            (None, "fp32", 1e-4), (None, "bf16x3", 1e-5)]:
+        if kern:
+            os.environ["DGCONV_FP64_KERNEL"] = kern
+        else:
+            os.environ.pop("DGCONV_FP64_KERNEL", None)
+        m = dg.Mesh.box(dim, 1, k)
+        ty = torch.float32 if prec == "fp32" else torch.float64
+        for uu in (None, u):
+            got = m.apply(dev(w, ty), None if uu is None else dev(uu, ty),
+                          precision=prec).double().cpu().numpy()
+            ref = sp.apply(w, uu)
+            e = rel_l2(sp, got, ref)
+            say("   %s %s %s: %.3e" % (kern, prec, "frozen" if uu is not None else "self", e))
+            assert e <= (tol if prec == "fp64" else 100 * tol)
+    os.environ.pop("DGCONV_FP64_KERNEL", None)
+
+
+def test_zero_substeps_and_zero_state(dg):
+    say("case zero substeps, zero state")
+    m = dg.Mesh.box(2, 8, 3)
+    sp = Space(box_mesh(2, 8), 3)
+    w = dev(initial_state(sp, seed=1))
+    w0 = w.clone()
+    m.rk_substeps(w, 1e-3, 0)
+    assert torch.equal(w, w0)
+    z = torch.zeros_like(w)
+    for prec in ("fp64", "bf16x3", "f16x2"):
+        r = m.apply(z, precision=prec)
+        assert not r.any(), prec
+    zf = torch.zeros(w.shape, dtype=torch.float32, device="cuda")
+    assert not m.apply(zf, precision="fp32").any()
