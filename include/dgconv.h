@@ -277,6 +277,19 @@ dg_status dg_surrogate_train_step(dg_surrogate* s, const float* x, const float* 
 dg_status dg_macro_step(const dg_mesh* mesh, dg_surrogate* s, double* w, double dt, double tol,
                         int* accepted, double* rho_out, void* stream);
 
+/* Learned initial guess for dg_richardson (the pseudo-time problem of Sec. 3.3,
+ * v + tau (M^V)^-1 C^V(u) v = g):
+ *   v = g + tau r(g) + sigma_T (s^3 tau^2 / h) net(inputs of g),  r(g) = -(M^V)^-1 C^V(u) g,
+ * s = max |g| over the volume points, inputs and sigma_T as for the macro-step.  The network
+ * predicts the solution's remainder beyond one explicit Euler step of size tau; it is trained
+ * with dg_surrogate_targets(w0 = g, w1 = the converged solution, r0 = r(g)).  g, v: dev FP64
+ * states, v aliasing neither g nor u; u: dev FP64 frozen velocity, or NULL for u := g.
+ * tau > 0 and finite.  Asynchronous on stream; uses workspace owned by s (calls on one
+ * surrogate must be serialised).  DG_EINVAL for null or misaligned pointers or a surrogate
+ * created for another mesh. */
+dg_status dg_surrogate_warm_start(const dg_mesh* mesh, dg_surrogate* s, const double* g,
+                                  const double* u, double tau, double* v, void* stream);
+
 /* The library's reference basis on the unit simplex (host): vals [n_pts][n_basis] and,
  * if grads is not NULL, reference gradients [n_pts][n_basis][dim] at pts [n_pts][dim]. */
 dg_status dg_eval_basis(int dim, int k, int64_t n_pts, const double* pts, double* vals,

@@ -78,6 +78,7 @@ def lib():
         "dg_surrogate_grad": [P, P, P, I64, P, P, P],
         "dg_surrogate_train_step": [P, P, P, I64, ctypes.c_float, P, P],
         "dg_macro_step": [P, P, P, D, D, P, P, P],
+        "dg_surrogate_warm_start": [P, P, P, P, D, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -375,3 +376,15 @@ class Surrogate:
                                    float(tol), ctypes.byref(acc), ctypes.byref(rho),
                                    _stream(stream)))
         return bool(acc.value), rho.value
+
+    def warm_start(self, g, u, tau, out=None, stream=None):
+        """Learned initial guess of the pseudo-time problem v + tau (M^V)^-1 C^V(u) v = g
+        (u None: u := g); returns out (allocated like g when None)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(g)
+        _check(lib().dg_surrogate_warm_start(self.mesh._h, self._h, _dev(g, torch.float64),
+                                             None if u is None else _dev(u, torch.float64),
+                                             float(tau), _dev(out, torch.float64),
+                                             _stream(stream)))
+        return out

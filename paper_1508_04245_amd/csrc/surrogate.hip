@@ -740,4 +740,32 @@ dg_status dg_macro_step(const dg_mesh* m, dg_surrogate* s, double* w, double dt,
   return DG_OK;
 }
 
+dg_status dg_surrogate_warm_start(const dg_mesh* m, dg_surrogate* s, const double* g,
+                                  const double* u, double tau, double* v, void* stream) {
+  if (!m || !s || !g || !v) return fail(DG_EINVAL, "null pointer");
+  if (!al16(g) || !al16(v) || (u && !al16(u)))
+    return fail(DG_EINVAL, "states must be 16-byte aligned");
+  if (!(tau > 0) || !std::isfinite(tau)) return fail(DG_EINVAL, "tau must be positive and finite");
+  if (m->h.E != s->E) return fail(DG_EINVAL, "surrogate was created for another mesh");
+  if (v == g || (u && v == u)) return fail(DG_EINVAL, "v must not alias g or u");
+  const hipStream_t hs = (hipStream_t)stream;
+  const int64_t E = s->E;
+  const int per = s->dim * s->np;
+  double* r0 = s->mwork + (size_t)E * per;
+  dg_status st = ensure_cap(s, E);
+  if (st != DG_OK) return st;
+  // r0 = r(g) with the frozen velocity, scale = max |g|, network inputs from g, forward pass,
+  // then v = g + tau r0 + sigma (s^3 tau^2 / h) y
+  if ((st = dg_convection_apply(m, DG_FP64, g, u, r0, stream)) != DG_OK) return st;
+  if ((st = dg_reduce(m, DG_RED_MAXVEL, g, nullptr, s->scale, stream)) != DG_OK) return st;
+  hipLaunchKernelGGL(features_kernel, dim3(nblk(E, 4)), dim3(256), 0, hs, E, s->dim, s->np,
+                     (const int32_t*)nullptr, s->nbr, s->sigma, g, s->scale, (float*)nullptr, s->xb);
+  HIP_TRY(hipGetLastError());
+  if ((st = forward(s, E, false, hs)) != DG_OK) return st;
+  hipLaunchKernelGGL(update_kernel, dim3(nblk(E * per)), dim3(256), 0, hs, E, per, s->sigma, g,
+                     r0, s->y, s->scale, tau, s->hmesh, v);
+  HIP_TRY(hipGetLastError());
+  return DG_OK;
+}
+
 }  // extern "C"

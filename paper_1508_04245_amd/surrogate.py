@@ -9,6 +9,10 @@ from the seeded random Fourier generator (16 modes, |kappa| <= 4, Leray-projecte
 amplitudes, unit RMS), projected onto the DG space; dt = 0.1 h / (k^2 max|w0|); one
 macro-step replaces M = 8 substeps.
 
+The same network also serves as a learned initial guess of the pseudo-time (Richardson)
+iteration for v + tau (M^V)^-1 C^V(u) v = g (Sec. 3.3) with u := g frozen, tau = 0.5 h / max|g|:
+trained on the remainder of the converged solution beyond g + tau r(g) (--warm-start).
+
 Usage: python -m paper_1508_04245_amd.surrogate [--train-seeds 2000] ...  (prints JSON)
 """
 import argparse
@@ -169,6 +173,97 @@ def timing(mesh, sur, dt, reps=20, M=8, device="cuda"):
     return t_plain, t_sur
 
 
+def richardson_problem(mesh, g, k=3, cfl=0.5):
+    """Pseudo-time problem v + tau (M^V)^-1 C^V(u) v = g with u := g frozen: tau = cfl h / s,
+    ds = 1 / (1 + tau (k+1)^2 s / h), s = max |g| (the step sizes the Richardson tests use)."""
+    h = 1.0 / round(np.sqrt(mesh.E / 2))
+    s0 = float(mesh.reduce("maxvel", g)[0].item())
+    tau = cfl * h / s0
+    ds = 1.0 / (1.0 + tau * (k + 1) ** 2 * s0 / h)
+    return tau, ds
+
+
+def warm_start_data(mesh, sur, seeds, per_seed, rtol=1e-10, max_it=4000, device="cuda"):
+    """Samples (x, t) for the learned warm start: inputs from g, targets from the converged
+    pseudo-time solution v* (remainder beyond g + tau r(g))."""
+    import torch
+    xs, ts = [], []
+    gen = torch.Generator(device=device)
+    work = None
+    for seed, g_host in zip(seeds, initial_states(mesh, list(seeds))):
+        gen.manual_seed(int(seed))
+        g = torch.tensor(g_host, device=device)
+        if work is None:
+            work = torch.empty_like(g)
+        tau, ds = richardson_problem(mesh, g)
+        v = g.clone()
+        mesh.richardson(v, g, g, tau, ds, rtol, max_it, work=work)
+        r0 = mesh.apply(g)
+        scale = mesh.reduce("maxvel", g)
+        elems = torch.randint(0, mesh.E, (per_seed,), generator=gen, device=device,
+                              dtype=torch.int32)
+        xs.append(sur.features(g, scale, elems))
+        ts.append(sur.targets(g, v, r0, scale, tau, elems))
+    return torch.cat(xs), torch.cat(ts)
+
+
+def warm_start_eval(mesh, sur, seeds, rel_tol=1e-6, max_it=4000, device="cuda"):
+    """Updates and time to reach a fixed absolute residual (rel_tol times the residual of the
+    plain start v0 = g) from three initial guesses: g, g + tau r(g), and the learned one."""
+    import torch
+    out = {name: {"updates": [], "err": [], "t_ms": []} for name in ("copy", "euler", "learned")}
+    work = None
+    for g_host in initial_states(mesh, list(seeds)):
+        g = torch.tensor(g_host, device=device)
+        if work is None:
+            work = torch.empty_like(g)
+        tau, ds = richardson_problem(mesh, g)
+        ref = g.clone()
+        mesh.richardson(ref, g, g, tau, ds, 1e-12, max_it, work=work)
+        inc = float(torch.linalg.norm(ref - g))
+        # the residual of an initial guess is evaluated with the first update
+        _, res_copy, _ = mesh.richardson(g.clone(), g, g, tau, ds, 0.0, 1, work=work)
+        atol = rel_tol * res_copy
+        starts = {"copy": lambda: g.clone(),
+                  "euler": lambda: g + tau * mesh.apply(g),
+                  "learned": lambda: sur.warm_start(g, g, tau)}
+        for name, make in starts.items():
+            v = make()
+            _, r0, _ = mesh.richardson(v.clone(), g, g, tau, ds, 0.0, 1, work=work)
+            out[name]["err"].append(float(torch.linalg.norm(v - ref)) / inc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            v = make()
+            n, _, _ = mesh.richardson(v, g, g, tau, ds, min(1.0, atol / r0), max_it, work=work)
+            torch.cuda.synchronize()
+            out[name]["t_ms"].append((time.perf_counter() - t0) * 1e3)
+            out[name]["updates"].append(n)
+    return {name: {key: float(np.median(val)) for key, val in d.items()} for name, d in out.items()}
+
+
+def warm_start_main(args):
+    """Train the network as a warm start of the pseudo-time iteration and compare initial
+    guesses (one JSON line)."""
+    import torch
+    mesh = Mesh.box(2, args.n, 3)
+    sur = Surrogate(mesh, M=8)
+    sur.load(init_params(0, sur.n_params))
+    log = lambda s: print(s, flush=True)
+    t0 = time.perf_counter()
+    X, T = warm_start_data(mesh, sur, range(1, args.train_seeds + 1), args.per_snapshot)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    log("generated %d samples in %.1f s" % (X.shape[0], t_gen))
+    t0 = time.perf_counter()
+    hist = train(sur, X, T, args.epochs, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    res = warm_start_eval(mesh, sur, range(10001, 10001 + args.eval_seeds))
+    print(json.dumps({"study": "warm_start", "samples": int(X.shape[0]), "t_generate_s": t_gen,
+                      "t_train_s": t_train, "loss_first": hist[0][1] if hist else None,
+                      "loss_last": hist[-1][1] if hist else None, "median": res}))
+
+
 def main():
     import torch
     ap = argparse.ArgumentParser()
@@ -180,7 +275,13 @@ def main():
     ap.add_argument("--eval-seeds", type=int, default=20)
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--out", default=None, help="save trained parameters (.npy)")
+    ap.add_argument("--warm-start", action="store_true",
+                    help="train and evaluate the network as an initial guess of the pseudo-time "
+                         "iteration instead (--per-snapshot elements per training seed)")
     args = ap.parse_args()
+    if args.warm_start:
+        warm_start_main(args)
+        return
     mesh = Mesh.box(2, args.n, 3)
     sur = Surrogate(mesh, M=8)
     sur.load(init_params(0, sur.n_params))

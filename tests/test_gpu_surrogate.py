@@ -145,3 +145,45 @@ def test_macro_step_fallback_paths(env):
     unit = scale[0] ** 3 * tau ** 2 / h
     cand = w + tau * mesh.apply(w) + (sign * unit)[:, None, None] * y.double().view(w.shape)
     assert torch.allclose(ws, cand, rtol=0, atol=1e-12)
+
+
+def test_warm_start_matches_its_definition(env):
+    """v = g + tau r(g) + sigma (s^3 tau^2 / h) net(inputs of g): against the library's own
+    pieces (the same kernels, 1e-12) and against the oracle operator and the FP64 network
+    oracle (the network term within the BF16 bar of this file)."""
+    from oracle.dg import Space
+    from oracle.mesh import box_mesh
+    dg, S, mesh, sur = env
+    say("case surrogate warm start")
+    p = mlp.init_params(13).astype(np.float32)
+    sur.load(p)
+    g_h = S.initial_state(mesh, 5)
+    u_h = S.initial_state(mesh, 6)
+    g = torch.tensor(g_h, device="cuda")
+    u = torch.tensor(u_h, device="cuda")
+    tau, h = 0.01, mesh.info["h_min"]
+    nb, _ = mesh.neighbors()
+    X = mesh.vertices()
+    sign_h = np.where(X[:, 1, 0] - X[:, 0, 0] < 0, -1.0, 1.0)
+    sign = torch.tensor(sign_h, device="cuda")
+    sp = Space(box_mesh(2, 16), 3)
+    for uu, uu_h in ((None, None), (u, u_h)):
+        v = sur.warm_start(g, uu, tau)
+        scale = mesh.reduce("maxvel", g)
+        y = sur.forward(sur.features(g, scale))
+        unit = scale[0] ** 3 * tau ** 2 / h
+        cand = g + tau * mesh.apply(g, uu) + (sign * unit)[:, None, None] * y.double().view(g.shape)
+        assert torch.allclose(v, cand, rtol=0, atol=1e-12)
+        s = float(scale[0].item())
+        yref = mlp.forward(p.astype(np.float64),
+                           mlp.features(g_h, nb, sign_h, s, np.arange(mesh.E))).reshape(g_h.shape)
+        net = (sign_h * s ** 3 * tau ** 2 / h)[:, None, None] * yref
+        base = g_h + tau * sp.apply(g_h, uu_h)
+        got = v.cpu().numpy()
+        e_net = np.linalg.norm(got - base - net) / np.linalg.norm(net)
+        say("   u %s: network term rel %.3e" % ("frozen" if uu is not None else "= g", e_net))
+        assert e_net < 3e-2
+    with pytest.raises(dg.DGError):
+        sur.warm_start(g, None, 0.0)
+    with pytest.raises(dg.DGError):
+        sur.warm_start(g, None, tau, out=g)
