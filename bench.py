@@ -210,7 +210,7 @@ def rows_study(dg, reps=50):
     """Timing of the rows beside the self-convection substeps, on the 2D 256x256x2 P4 mesh
     (FP64, inputs resident): frozen-velocity substeps, substeps with the velocity extrapolated
     in time, the pseudo-time (Richardson) update, substeps on the bounded channel, and the
-    H(div) <-> DG transfers.  One JSON line per row, with its HBM-byte equivalent (algorithmic
+    H(div) <-> DG transfers (also on the 3D 32^3 x 6 P3 mesh).  One JSON line per row, with its HBM-byte equivalent (algorithmic
     bytes: state reads and writes, neighbour states counted once, geometry)."""
     import torch
     from paper_1508_04245_amd import synth
@@ -237,8 +237,9 @@ def rows_study(dg, reps=50):
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1) / 1e3 / n
 
-    def emit(row, sec, launches, byts, extra=None):
-        out = {"row": row, "workload": "2D periodic 256x256x2 triangles, P4, FP64",
+    def emit(row, sec, launches, byts, extra=None,
+             workload="2D periodic 256x256x2 triangles, P4, FP64"):
+        out = {"row": row, "workload": workload,
                "s_per_call": sec, "us_per_launch": sec / launches * 1e6,
                "hbm_equiv_GBps": byts / (sec / launches) / 1e9}
         out.update(extra or {})
@@ -277,8 +278,25 @@ def rows_study(dg, reps=50):
     emit("transfer I (W_h -> V_h)", t, 1, n_w * 8 + st + E * 44, {"n_hdiv": n_w})
     gt = torch.empty(n_w, dtype=torch.float64, device=dev)
     t = timed(lambda: m.transfer_transpose(w, out=gt), reps)
-    emit("transfer I^T (V_h' -> W_h')", t, 2, st + 2 * E * 2 * m.np * 8 + n_w * 8 + E * 44,
+    # bytes of both passes, reported per launch as their mean
+    emit("transfer I^T (V_h' -> W_h')", t, 2, (st + 2 * E * 2 * m.np * 8 + n_w * 8 + E * 44) / 2,
          {"n_hdiv": n_w})
+    # the same transfers in 3D on the 32^3 x 6 tetrahedra P3 mesh (facet codes 16 B and J^-1
+    # 72 B per element)
+    m3 = dg.Mesh.box(3, 32, 3)
+    E3 = m3.info["n_elem"]
+    st3 = m3.info["n_dof"] * 8
+    n_w3, _ = m3.hdiv_size()
+    uh3 = torch.randn(n_w3, dtype=torch.float64, device=dev)
+    out3 = torch.empty((E3, 3, m3.np), dtype=torch.float64, device=dev)
+    wl3 = "3D periodic 32^3 x 6 tetrahedra, P3, FP64"
+    t = timed(lambda: m3.to_dg(uh3, out=out3), reps)
+    emit("transfer I (W_h -> V_h)", t, 1, n_w3 * 8 + st3 + E3 * 88, {"n_hdiv": n_w3},
+         workload=wl3)
+    gt3 = torch.empty(n_w3, dtype=torch.float64, device=dev)
+    t = timed(lambda: m3.transfer_transpose(out3, out=gt3), reps)
+    emit("transfer I^T (V_h' -> W_h')", t, 2, (st3 + 2 * st3 + n_w3 * 8 + E3 * 88) / 2,
+         {"n_hdiv": n_w3}, workload=wl3)
 
 
 def main():

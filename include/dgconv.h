@@ -188,28 +188,36 @@ dg_status dg_rk_substeps_extrap(const dg_mesh* mesh, dg_precision prec, void* w,
                                 double tb, void* work, void* stream);
 
 /* Transfer between the H(div)-conforming velocity space W_h and the DG space V_h (Sec. 2.4,
- * eq. l2I; 2D meshes, 1 <= k <= 6).  W_h (Sec. 2.2: element-wise [P^k]^2 fields with
- * continuous normal components) carries the Brezzi-Douglas-Marini degrees of freedom:
- *   facet    int_F (v . n_F) q_l(s) ds, l = 0..k: n_F the outward normal of the lower-numbered
- *            element sharing F (of its element on a boundary facet), s in [0, 1] along F from
- *            its lexicographically first vertex, q_l(s) = sqrt(2l+1) P_l(2s-1);
+ * eq. l2I; 2D meshes with 1 <= k <= 6, 3D meshes with 1 <= k <= 3).  W_h (Sec. 2.2:
+ * element-wise [P^k]^d fields with continuous normal components) carries the
+ * Brezzi-Douglas-Marini degrees of freedom:
+ *   facet    int_F (v . n_F) q_l ds over an L2-orthonormal basis of P^k(F): n_F the outward
+ *            normal of the lower-numbered element sharing F (of its element on a boundary
+ *            facet); the facet parameter runs from its canonical vertices (lexicographic
+ *            order), A + s (B - A) [+ t (C - A)]; 2D: q_l(s) = sqrt(2l+1) P_l(2s-1), l = 0..k;
+ *            3D: q_l(s, t) = phi_l(s, t) / sqrt(2), phi_l the library's basis of the reference
+ *            triangle (dg_eval_basis with dim 2), (k+1)(k+2)/2 functions;
  *   interior sign(det J) int_T v . (J^-T psi_r(F_T^-1 x)) dx, psi_r over the first-kind
- *            Nedelec space N_{k-1} of the reference triangle: (x^a y^b, 0), (0, x^a y^b) for
- *            a + b <= k-2 (degree ascending, a descending), then (-y, x) x^a y^b for a + b = k-2.
- * W_h coefficients u are the values of these functionals: the k+1 dofs of each facet (facets
- * in the order of their owner element, then local facet), then the k^2-1 interior dofs of
- * each element.  The numbering and device tables are built on the first transfer call
+ *            Nedelec space N_{k-1} of the reference simplex: e_i x^a y^b [z^c] for total
+ *            degree <= k-2, then the rotations of the monomials m of degree k-2: (-y, x) m in
+ *            2D, x ^ (e_i m) in 3D without i = 0 when x divides m; monomials by degree, a
+ *            descending, then b descending, i ascending for each (k^2-1 functions in 2D,
+ *            (k-1)(k+1)(k+2)/2 in 3D).
+ * W_h coefficients u are the values of these functionals: the dofs of each facet (facets in
+ * the order of their owner element, then local facet), then the interior dofs of each
+ * element.  The numbering and device tables are built on the first transfer call
  * (synchronous).
  * dg_hdiv_info: *n_dof = dim W_h, *n_facet (may be NULL) = facets (host, synchronous).
- * dg_hdiv_reference: the reference dual basis, host [(k+1)(k+2)][2][n_basis] (dof j, then
- * its DG coefficients on e_a phi_m of the reference triangle).
+ * dg_hdiv_reference: the reference dual basis, host [dim n_basis][dim][n_basis] (dof j in
+ * local order: the facets' moments in each local facet's ascending-vertex parameter, then the
+ * interior ones; then its DG coefficients on e_a phi_m of the reference simplex).
  * dg_transfer_to_dg: w_out = I u = (M^V)^-1 M^{U,V} u, the DG coefficients of the W_h field
  * (u: dev [n_dof] doubles; w_out: dev FP64 state).
  * dg_transfer_transpose: g_out = I^T f (f: dev FP64 state holding a functional's values on
  * the DG basis; g_out: dev [n_dof]); uses a mesh-owned work buffer, so calls on one mesh
- * must be serialised.  Errors: DG_EUNSUPPORTED (3D mesh), DG_EINVAL (k, null pointers). */
+ * must be serialised.  Errors: DG_EINVAL (dim, k, null pointers, aliasing). */
 dg_status dg_hdiv_info(const dg_mesh* mesh, int64_t* n_dof, int64_t* n_facet);
-dg_status dg_hdiv_reference(int k, double* table_out);
+dg_status dg_hdiv_reference(int dim, int k, double* table_out);
 dg_status dg_transfer_to_dg(const dg_mesh* mesh, const double* u, double* w_out, void* stream);
 dg_status dg_transfer_transpose(const dg_mesh* mesh, const double* f, double* g_out,
                                 void* stream);

@@ -59,7 +59,7 @@ def lib():
         "dg_rk_substeps_extrap": [P, I, P, D, I, D, P, D, P, D, P, P],
         "dg_boundary_points": [P, P],
         "dg_hdiv_info": [P, P, P],
-        "dg_hdiv_reference": [I, P],
+        "dg_hdiv_reference": [I, I, P],
         "dg_transfer_to_dg": [P, P, P, P],
         "dg_transfer_transpose": [P, P, P, P],
         "dg_convection_apply_bc": [P, I, P, P, P, P, P, P],
@@ -193,7 +193,7 @@ class Mesh:
         return out
 
     def hdiv_size(self):
-        """(dim W_h, number of facets) of the H(div) space (2D, k >= 1)."""
+        """(dim W_h, number of facets) of the H(div) space (2D: 1 <= k <= 6; 3D: 1 <= k <= 3)."""
         n, nf = ctypes.c_int64(0), ctypes.c_int64(0)
         _check(lib().dg_hdiv_info(self._h, ctypes.byref(n), ctypes.byref(nf)))
         return n.value, nf.value

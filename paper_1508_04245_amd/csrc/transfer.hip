@@ -1,16 +1,16 @@
-// Transfer operators between the H(div) space W_h and the DG space V_h on 2D meshes
+// Transfer operators between the H(div) space W_h and the DG space V_h on 2D and 3D meshes
 // (Sec. 2.4): I = (M^V)^-1 M^{U,V} (the DG coefficients of a W_h field) and its transpose
 // I^T (a functional on V_h, given by its values on the DG basis, to one on W_h).
 //
-// On element T a W_h field is sum_j s_j u_J(j) Piola(psi^_j), so with the signed Piola map
-// v = J v^ / det J its DG coefficients are
-//   c[i][m] = sum_a (J / det J)_ia ref[a][m],   ref[a][m] = sum_j s_j u_J(j) C_j[a][m],
+// On element T a W_h field is Piola(sum_j (P u_T)_j psi^_j), P the local map (facet signs and
+// parameter changes), so with the signed Piola map v = J v^ / det J its DG coefficients are
+//   c[i][m] = sum_a (J / det J)_ia ref[a][m],   ref[a][m] = sum_j (P u_T)_j C_j[a][m],
 // and J / det J is the adjugate of J^-1, which the mesh already stores.  One lane per element;
-// the reference dual basis C (ndof x 2 x np doubles) sits in LDS and is read with wave-uniform
-// addresses.  The transpose runs in two passes: every element writes the signed contributions
-// s_j sum_{a,m} C_j[a][m] G[a][m] (G = adj(J^-1)^T F) of its local dofs, then every global dof
-// adds its one (interior, boundary facet) or two (interior facet) contributions in a fixed
-// order, so the result is deterministic and needs no atomics.
+// the reference dual basis C (ndof x d x np doubles) and, in 3D, the six facet parameter
+// changes sit in LDS.  The transpose runs in two passes: every element writes the
+// contributions P^T (C^T G) of its local dofs (G = adj(J^-1)^T F), then every global dof adds
+// its one (interior, boundary facet) or two (interior facet) contributions in a fixed order,
+// so the result is deterministic and needs no atomics.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,115 +23,191 @@ namespace {
 
 using dgi::fail;
 
-template <int K>
+template <int D, int K>
 struct HShape {
-  static constexpr int NP = (K + 1) * (K + 2) / 2, ND = 2 * NP, NFD = K + 1, NI = K * K - 1;
+  static constexpr int NP = D == 2 ? (K + 1) * (K + 2) / 2 : (K + 1) * (K + 2) * (K + 3) / 6;
+  static constexpr int ND = D * NP;
+  static constexpr int NFD = D == 2 ? K + 1 : (K + 1) * (K + 2) / 2;
+  static constexpr int NI = ND - (D + 1) * NFD;
+  static constexpr int NQ = D == 3 ? 6 * NFD * NFD : 0;  // facet parameter changes (3D)
+  static constexpr int TAB = ND * ND + NQ;
 };
 
-template <int K>
+// facet code of an element's local facet: global facet id, facet sign, 3D permutation code
+template <int D>
+struct FacetCode {
+  int64_t id;
+  double sf;  // sign(det J) times the normal sign
+  int perm;   // 2D: 1 = local parameter reversed; 3D: permutation code 0..5
+  __device__ explicit FacetCode(int c) {
+    if constexpr (D == 2) {
+      id = c >> 2; sf = (c & 2) ? -1.0 : 1.0; perm = c & 1;
+    } else {
+      id = c >> 4; sf = (c & 8) ? -1.0 : 1.0; perm = c & 7;
+    }
+  }
+};
+
+// adj(J^-1) = J / det J from the stored J^-1 (row-major)
+template <int D>
+__device__ __forceinline__ void adjugate(const double* m, double (&A)[D][D]) {
+  if constexpr (D == 2) {
+    A[0][0] = m[3]; A[0][1] = -m[1]; A[1][0] = -m[2]; A[1][1] = m[0];
+  } else {
+    A[0][0] = m[4] * m[8] - m[5] * m[7];
+    A[0][1] = m[2] * m[7] - m[1] * m[8];
+    A[0][2] = m[1] * m[5] - m[2] * m[4];
+    A[1][0] = m[5] * m[6] - m[3] * m[8];
+    A[1][1] = m[0] * m[8] - m[2] * m[6];
+    A[1][2] = m[2] * m[3] - m[0] * m[5];
+    A[2][0] = m[3] * m[7] - m[4] * m[6];
+    A[2][1] = m[1] * m[6] - m[0] * m[7];
+    A[2][2] = m[0] * m[4] - m[1] * m[3];
+  }
+}
+
+template <int D, int K>
 __global__ void __launch_bounds__(256) to_dg_kernel(int64_t E, int64_t nfd, const double* u,
                                                     const int* hf, const double* jinv,
                                                     const double* tab, double* out) {
-  using S = HShape<K>;
-  __shared__ double st[S::ND * S::ND];
-  for (int i = threadIdx.x; i < S::ND * S::ND; i += 256) st[i] = tab[i];
+  using S = HShape<D, K>;
+  __shared__ double st[S::TAB];
+  for (int i = threadIdx.x; i < S::TAB; i += 256) st[i] = tab[i];
   __syncthreads();
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= E) return;
-  double ref[2][S::NP];
+  double ref[D][S::NP];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < D; ++a)
 #pragma unroll
     for (int m = 0; m < S::NP; ++m) ref[a][m] = 0.0;
   auto accumulate = [&](int j, double uj) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < D; ++a)
 #pragma unroll
-      for (int m = 0; m < S::NP; ++m) ref[a][m] = fma(uj, st[(j * 2 + a) * S::NP + m], ref[a][m]);
+      for (int m = 0; m < S::NP; ++m) ref[a][m] = fma(uj, st[(j * D + a) * S::NP + m], ref[a][m]);
   };
-  // facet dofs with their signs (reference dof order), then the interior dofs
+  // facet dofs in local form (reference dof order), then the interior dofs
 #pragma unroll
-  for (int f = 0; f < 3; ++f) {
-    const int code = hf[t * 3 + f];
-    const int64_t id = code >> 2;
-    const double sf = (code & 2) ? -1.0 : 1.0;
-    const double so = (code & 1) ? -sf : sf;  // odd l under a reversed parameter
+  for (int f = 0; f <= D; ++f) {
+    const FacetCode<D> fc(hf[t * (D + 1) + f]);
+    const double* uf = u + fc.id * S::NFD;
+    if constexpr (D == 2) {
+      const double so = fc.perm ? -fc.sf : fc.sf;  // odd l under a reversed parameter
 #pragma unroll 1
-    for (int l = 0; l < S::NFD; ++l) accumulate(f * S::NFD + l, ((l & 1) ? so : sf) * u[id * S::NFD + l]);
+      for (int l = 0; l < S::NFD; ++l) accumulate(f * S::NFD + l, ((l & 1) ? so : fc.sf) * uf[l]);
+    } else {
+      double ug[S::NFD];
+#pragma unroll
+      for (int i = 0; i < S::NFD; ++i) ug[i] = uf[i];
+      const double* Q = st + S::ND * S::ND + fc.perm * S::NFD * S::NFD;
+#pragma unroll 1
+      for (int l = 0; l < S::NFD; ++l) {
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < S::NFD; ++i) v = fma(Q[l * S::NFD + i], ug[i], v);
+        accumulate(f * S::NFD + l, fc.sf * v);
+      }
+    }
   }
   const double* ui = u + nfd + t * S::NI;
 #pragma unroll 1
-  for (int r = 0; r < S::NI; ++r) accumulate(3 * S::NFD + r, ui[r]);
-  // J / det J = adj(J^-1) = [[ji11, -ji01], [-ji10, ji00]]
-  const double* ji = jinv + t * 4;
-  const double A[2][2] = {{ji[3], -ji[1]}, {-ji[2], ji[0]}};
+  for (int r = 0; r < S::NI; ++r) accumulate((D + 1) * S::NFD + r, ui[r]);
+  double A[D][D];
+  adjugate<D>(jinv + t * D * D, A);
   double* o = out + t * S::ND;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int m = 0; m < S::NP; ++m) o[i * S::NP + m] = fma(A[i][0], ref[0][m], A[i][1] * ref[1][m]);
+    for (int m = 0; m < S::NP; ++m) {
+      double v = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) v = fma(A[i][a], ref[a][m], v);
+      o[i * S::NP + m] = v;
+    }
 }
 
-template <int K>
+template <int D, int K>
 __global__ void __launch_bounds__(256) transpose_local_kernel(int64_t E, const double* F,
                                                               const int* hf, const double* jinv,
                                                               const double* tab, double* loc) {
-  using S = HShape<K>;
-  __shared__ double st[S::ND * S::ND];
-  for (int i = threadIdx.x; i < S::ND * S::ND; i += 256) st[i] = tab[i];
+  using S = HShape<D, K>;
+  __shared__ double st[S::TAB];
+  for (int i = threadIdx.x; i < S::TAB; i += 256) st[i] = tab[i];
   __syncthreads();
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= E) return;
-  const double* ji = jinv + t * 4;
-  const double A[2][2] = {{ji[3], -ji[1]}, {-ji[2], ji[0]}};
+  double A[D][D];
+  adjugate<D>(jinv + t * D * D, A);
   const double* f = F + t * S::ND;
-  double G[2][S::NP];  // G[a][m] = sum_i A[i][a] F[i][m]
+  double G[D][S::NP];  // G[a][m] = sum_i A[i][a] F[i][m]
 #pragma unroll
   for (int m = 0; m < S::NP; ++m) {
-    const double f0 = f[m], f1 = f[S::NP + m];
+    double fi[D];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) G[a][m] = fma(A[0][a], f0, A[1][a] * f1);
+    for (int i = 0; i < D; ++i) fi[i] = f[i * S::NP + m];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      double v = 0.0;
+#pragma unroll
+      for (int i = 0; i < D; ++i) v = fma(A[i][a], fi[i], v);
+      G[a][m] = v;
+    }
   }
   double* o = loc + t * S::ND;
   auto contract = [&](int j) {
     double acc = 0.0;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < D; ++a)
 #pragma unroll
-      for (int m = 0; m < S::NP; ++m) acc = fma(st[(j * 2 + a) * S::NP + m], G[a][m], acc);
+      for (int m = 0; m < S::NP; ++m) acc = fma(st[(j * D + a) * S::NP + m], G[a][m], acc);
     return acc;
   };
 #pragma unroll
-  for (int fc = 0; fc < 3; ++fc) {
-    const int code = hf[t * 3 + fc];
-    const double sf = (code & 2) ? -1.0 : 1.0;
-    const double so = (code & 1) ? -sf : sf;  // odd l under a reversed parameter
+  for (int fcn = 0; fcn <= D; ++fcn) {
+    const FacetCode<D> fc(hf[t * (D + 1) + fcn]);
+    if constexpr (D == 2) {
+      const double so = fc.perm ? -fc.sf : fc.sf;  // odd l under a reversed parameter
 #pragma unroll 1
-    for (int l = 0; l < S::NFD; ++l) {
-      const int j = fc * S::NFD + l;
-      o[j] = ((l & 1) ? so : sf) * contract(j);
+      for (int l = 0; l < S::NFD; ++l) {
+        const int j = fcn * S::NFD + l;
+        o[j] = ((l & 1) ? so : fc.sf) * contract(j);
+      }
+    } else {
+      // local values c_l, then the canonical contributions sf sum_l Q_li c_l
+      double cl[S::NFD];
+#pragma unroll
+      for (int l = 0; l < S::NFD; ++l) cl[l] = contract(fcn * S::NFD + l);
+      const double* Q = st + S::ND * S::ND + fc.perm * S::NFD * S::NFD;
+#pragma unroll 1
+      for (int i = 0; i < S::NFD; ++i) {
+        double v = 0.0;
+#pragma unroll
+        for (int l = 0; l < S::NFD; ++l) v = fma(Q[l * S::NFD + i], cl[l], v);
+        o[fcn * S::NFD + i] = fc.sf * v;
+      }
     }
   }
 #pragma unroll 1
-  for (int j = 3 * S::NFD; j < S::ND; ++j) o[j] = contract(j);
+  for (int j = (D + 1) * S::NFD; j < S::ND; ++j) o[j] = contract(j);
 }
 
-template <int K>
+template <int D, int K>
 __global__ void __launch_bounds__(256) transpose_gather_kernel(int64_t N, int64_t nfd,
                                                                const int64_t* fe,
                                                                const double* loc, double* out) {
-  using S = HShape<K>;
+  using S = HShape<D, K>;
   const int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (d >= N) return;
   if (d < nfd) {
     const int64_t fc = d / S::NFD, l = d % S::NFD;
     const int64_t s0 = fe[2 * fc], s1 = fe[2 * fc + 1];
-    double v = loc[(s0 / 3) * S::ND + (s0 % 3) * S::NFD + l];
-    if (s1 >= 0) v += loc[(s1 / 3) * S::ND + (s1 % 3) * S::NFD + l];
+    double v = loc[(s0 / (D + 1)) * S::ND + (s0 % (D + 1)) * S::NFD + l];
+    if (s1 >= 0) v += loc[(s1 / (D + 1)) * S::ND + (s1 % (D + 1)) * S::NFD + l];
     out[d] = v;
   } else {
     const int64_t t = (d - nfd) / S::NI, r = (d - nfd) % S::NI;
-    out[d] = loc[t * S::ND + 3 * S::NFD + r];
+    out[d] = loc[t * S::ND + (D + 1) * S::NFD + r];
   }
 }
 
@@ -160,30 +236,38 @@ dg_status ensure_hdiv(const dg_mesh* cm) {
   return DG_OK;
 }
 
-template <int K>
+template <int D, int K>
 dg_status run_to_dg(const dg_mesh* m, const double* u, double* out, hipStream_t s) {
-  const int64_t E = m->h.E, nfd = m->hd.nfacet * (K + 1);
-  hipLaunchKernelGGL(to_dg_kernel<K>, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, s, E,
+  if (m->hd.table.size() != (size_t)HShape<D, K>::TAB || m->hd.ndof != HShape<D, K>::ND)
+    return fail(DG_EINVAL, "H(div) tables do not match the kernel");
+  const int64_t E = m->h.E, nfd = m->hd.nfacet * HShape<D, K>::NFD;
+  hipLaunchKernelGGL((to_dg_kernel<D, K>), dim3((unsigned)((E + 255) / 256)), dim3(256), 0, s, E,
                      nfd, u, m->d_hfacet, m->d_jinv, m->d_htab, out);
   HIP_TRY(hipGetLastError());
   return DG_OK;
 }
 
-template <int K>
+template <int D, int K>
 dg_status run_transpose(const dg_mesh* m, const double* F, double* out, hipStream_t s) {
-  const int64_t E = m->h.E, nfd = m->hd.nfacet * (K + 1), N = m->hd.N;
-  hipLaunchKernelGGL(transpose_local_kernel<K>, dim3((unsigned)((E + 255) / 256)), dim3(256), 0,
+  if (m->hd.table.size() != (size_t)HShape<D, K>::TAB || m->hd.ndof != HShape<D, K>::ND)
+    return fail(DG_EINVAL, "H(div) tables do not match the kernel");
+  const int64_t E = m->h.E, nfd = m->hd.nfacet * HShape<D, K>::NFD, N = m->hd.N;
+  hipLaunchKernelGGL((transpose_local_kernel<D, K>), dim3((unsigned)((E + 255) / 256)), dim3(256), 0,
                      s, E, F, m->d_hfacet, m->d_jinv, m->d_htab, m->d_hlocal);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(transpose_gather_kernel<K>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
+  hipLaunchKernelGGL((transpose_gather_kernel<D, K>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
                      s, N, nfd, m->d_hfelem, m->d_hlocal, out);
   HIP_TRY(hipGetLastError());
   return DG_OK;
 }
 
+// degrees with kernels: 1..6 in 2D, 1..3 in 3D (the 3D tables fill the LDS beyond)
+bool hdiv_degree_ok(int dim, int k) { return k >= 1 && k <= (dim == 2 ? 6 : 3); }
+
 dg_status prepare(const dg_mesh* m) {
-  if (m->h.dim != 2) return fail(DG_EUNSUPPORTED, "the H(div) transfer is built for 2D meshes");
-  if (m->h.k < 1 || m->h.k > 6) return fail(DG_EINVAL, "the H(div) transfer needs 1 <= k <= 6");
+  if (m->h.dim != 2 && m->h.dim != 3) return fail(DG_EINVAL, "the H(div) transfer needs dim 2 or 3");
+  if (!hdiv_degree_ok(m->h.dim, m->h.k))
+    return fail(DG_EINVAL, "the H(div) transfer needs 1 <= k <= 6 (2D) or 1 <= k <= 3 (3D)");
   dg_status st = dgi::ensure_device(m);
   if (st != DG_OK) return st;
   return ensure_hdiv(m);
@@ -195,8 +279,9 @@ extern "C" {
 
 dg_status dg_hdiv_info(const dg_mesh* m, int64_t* n_dof, int64_t* n_facet) {
   if (!m || !n_dof) return fail(DG_EINVAL, "null pointer");
-  if (m->h.dim != 2) return fail(DG_EUNSUPPORTED, "the H(div) transfer is built for 2D meshes");
-  if (m->h.k < 1) return fail(DG_EINVAL, "the H(div) transfer needs k >= 1");
+  if (m->h.dim != 2 && m->h.dim != 3) return fail(DG_EINVAL, "the H(div) transfer needs dim 2 or 3");
+  if (!hdiv_degree_ok(m->h.dim, m->h.k))
+    return fail(DG_EINVAL, "the H(div) transfer needs 1 <= k <= 6 (2D) or 1 <= k <= 3 (3D)");
   dghdiv::Host hd;
   std::string err;
   const int rc = dghdiv::build(m->h, hd, err);
@@ -206,11 +291,12 @@ dg_status dg_hdiv_info(const dg_mesh* m, int64_t* n_dof, int64_t* n_facet) {
   return DG_OK;
 }
 
-dg_status dg_hdiv_reference(int k, double* table_out) {
+dg_status dg_hdiv_reference(int dim, int k, double* table_out) {
   if (!table_out) return fail(DG_EINVAL, "null pointer");
-  if (k < 1 || k > 6) return fail(DG_EINVAL, "k must be in 1..6");
+  if ((dim != 2 && dim != 3) || !hdiv_degree_ok(dim, k))
+    return fail(DG_EINVAL, "need dim 2 with k in 1..6 or dim 3 with k in 1..3");
   std::vector<double> t;
-  dghdiv::reference_dual(k, t);
+  dghdiv::reference_dual(dim, k, t);
   std::memcpy(table_out, t.data(), t.size() * sizeof(double));
   return DG_OK;
 }
@@ -221,13 +307,20 @@ dg_status dg_transfer_to_dg(const dg_mesh* m, const double* u, double* w_out, vo
   dg_status st = prepare(m);
   if (st != DG_OK) return st;
   const hipStream_t s = (hipStream_t)stream;
+  if (m->h.dim == 3) {
+    switch (m->h.k) {
+      case 1: return run_to_dg<3, 1>(m, u, w_out, s);
+      case 2: return run_to_dg<3, 2>(m, u, w_out, s);
+      default: return run_to_dg<3, 3>(m, u, w_out, s);
+    }
+  }
   switch (m->h.k) {
-    case 1: return run_to_dg<1>(m, u, w_out, s);
-    case 2: return run_to_dg<2>(m, u, w_out, s);
-    case 3: return run_to_dg<3>(m, u, w_out, s);
-    case 4: return run_to_dg<4>(m, u, w_out, s);
-    case 5: return run_to_dg<5>(m, u, w_out, s);
-    default: return run_to_dg<6>(m, u, w_out, s);
+    case 1: return run_to_dg<2, 1>(m, u, w_out, s);
+    case 2: return run_to_dg<2, 2>(m, u, w_out, s);
+    case 3: return run_to_dg<2, 3>(m, u, w_out, s);
+    case 4: return run_to_dg<2, 4>(m, u, w_out, s);
+    case 5: return run_to_dg<2, 5>(m, u, w_out, s);
+    default: return run_to_dg<2, 6>(m, u, w_out, s);
   }
 }
 
@@ -238,13 +331,20 @@ dg_status dg_transfer_transpose(const dg_mesh* m, const double* f, double* g_out
   dg_status st = prepare(m);
   if (st != DG_OK) return st;
   const hipStream_t s = (hipStream_t)stream;
+  if (m->h.dim == 3) {
+    switch (m->h.k) {
+      case 1: return run_transpose<3, 1>(m, f, g_out, s);
+      case 2: return run_transpose<3, 2>(m, f, g_out, s);
+      default: return run_transpose<3, 3>(m, f, g_out, s);
+    }
+  }
   switch (m->h.k) {
-    case 1: return run_transpose<1>(m, f, g_out, s);
-    case 2: return run_transpose<2>(m, f, g_out, s);
-    case 3: return run_transpose<3>(m, f, g_out, s);
-    case 4: return run_transpose<4>(m, f, g_out, s);
-    case 5: return run_transpose<5>(m, f, g_out, s);
-    default: return run_transpose<6>(m, f, g_out, s);
+    case 1: return run_transpose<2, 1>(m, f, g_out, s);
+    case 2: return run_transpose<2, 2>(m, f, g_out, s);
+    case 3: return run_transpose<2, 3>(m, f, g_out, s);
+    case 4: return run_transpose<2, 4>(m, f, g_out, s);
+    case 5: return run_transpose<2, 5>(m, f, g_out, s);
+    default: return run_transpose<2, 6>(m, f, g_out, s);
   }
 }
 

@@ -224,30 +224,34 @@ def test_boundary_mesh_needs_the_bc_entry_points():
                            None) == -4
 
 
-@pytest.mark.parametrize("k", [1, 2, 4, 6])
-def test_hdiv_reference_basis_matches_the_oracle(k):
+@pytest.mark.parametrize("dim,k", [(2, 1), (2, 2), (2, 4), (2, 6), (3, 1), (3, 2), (3, 3)])
+def test_hdiv_reference_basis_matches_the_oracle(dim, k):
     """The library's reference dual basis (long double Gauss-Jordan of its own moment matrix)
     equals the oracle's (NumPy inverse), dof by dof."""
+    from oracle import refelem as R
     from oracle.hdiv import reference_dual
-    nb = (k + 1) * (k + 2) // 2
-    tab = np.zeros(((k + 1) * (k + 2), 2, nb))
-    assert dg.lib().dg_hdiv_reference(k, dg._ptr(tab)) == 0
-    C = reference_dual(k)  # [(a, m), j]
-    ref = C.T.reshape(-1, 2, nb)
+    nb = R.n_basis(dim, k)
+    tab = np.zeros((dim * nb, dim, nb))
+    assert dg.lib().dg_hdiv_reference(dim, k, dg._ptr(tab)) == 0
+    C = reference_dual(dim, k)  # [(a, m), j]
+    ref = C.T.reshape(-1, dim, nb)
     assert np.abs(tab - ref).max() < 1e-9 * np.abs(ref).max()
+    assert dg.lib().dg_hdiv_reference(dim, 7 if dim == 2 else 4, dg._ptr(tab)) == -1
 
 
 def test_hdiv_size_matches_the_oracle():
     from oracle.hdiv import HdivSpace
     from oracle.mesh import box_mesh
-    for per in [(True, True), (False, True)]:
-        om = box_mesh(2, 4, jitter=0.1, seed=2, periodic=per)
+    for dim, per, k in [(2, (True, True), 3), (2, (False, True), 3), (3, (True, True, True), 2),
+                        (3, (False, True, False), 3)]:
+        om = box_mesh(dim, 4 if dim == 2 else 2, jitter=0.1, seed=2, periodic=per)
         E = om.E
-        m = dg.Mesh.from_arrays(2, 3, om.X.reshape(-1, 2), np.arange(E * 3).reshape(E, 3),
+        m = dg.Mesh.from_arrays(dim, k, om.X.reshape(-1, dim),
+                                np.arange(E * (dim + 1)).reshape(E, dim + 1),
                                 np.where(per, 1.0, 0.0))
-        H = HdivSpace(om, 3)
+        H = HdivSpace(om, k)
         assert m.hdiv_size() == (H.N, H.n_facets)
-    m3 = dg.Mesh.box(3, 2, 2)
+    m3 = dg.Mesh.box(3, 2, 4)
     with pytest.raises(dg.DGError) as e:
         m3.hdiv_size()
-    assert e.value.status == -4
+    assert e.value.status == -1
