@@ -31,8 +31,8 @@ TRAFFIC_SOURCES = ("paper_1508_04245_amd/csrc/conv_kernels.hpp",
                    "paper_1508_04245_amd/csrc/mfma_kernels.hpp",
                    "paper_1508_04245_amd/csrc/dgconv.hip")
 MEASURED_TRAFFIC = {
-    ("c2", "fp64", "valu"): (110.1e6, "517776f0e0e34b62"),
-    ("c3", "fp64", "mfma"): (428.4e6, "517776f0e0e34b62"),
+    ("c2", "fp64", "valu"): (111.4e6, "06e7779eebbf8cac"),
+    ("c3", "fp64", "mfma"): (428.4e6, "06e7779eebbf8cac"),
 }
 
 
@@ -195,6 +195,8 @@ def precision_study(dg, cfgs, tol=1e-6):
             err = float(d[0].item() / d[1].item())
             rows.append({"precision": prec, "kernel": kern or "default", "rel_l2_vs_fp64": err,
                          "s_per_substep": t})
+            print("%s %s/%s: %.1f us per substep" % (name, prec, kern or "default", t * 1e6),
+                  file=sys.stderr, flush=True)
             del m
         os.environ.pop("DGCONV_FP64_KERNEL", None)
         t64 = rows[0]["s_per_substep"]
@@ -316,6 +318,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--rows", action="store_true",
                     help="time the rows beside the self-convection substeps (one JSON line each)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only a plain 512 MiB device copy, three times (the reference "
+                         "dispatch for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--precision-study", default=None, metavar="CFGS",
                     help="comma-separated configs: final-state error and speedup of every "
                          "precision variant against FP64 (one JSON line per config)")
@@ -331,6 +336,14 @@ def main():
     import torch
     import paper_1508_04245_amd as dg
     dg.lib()
+    if args.copy_calibration:
+        x = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 8, "copies": 3}), flush=True)
+        return
     if args.precision_study:
         precision_study(dg, args.precision_study.split(","))
         return
