@@ -188,7 +188,7 @@ dg_status dg_rk_substeps_extrap(const dg_mesh* mesh, dg_precision prec, void* w,
                                 double tb, void* work, void* stream);
 
 /* Transfer between the H(div)-conforming velocity space W_h and the DG space V_h (Sec. 2.4,
- * eq. l2I; 2D meshes with 1 <= k <= 6, 3D meshes with 1 <= k <= 3).  W_h (Sec. 2.2:
+ * eq. l2I; 2D meshes with 1 <= k <= 6, 3D meshes with 1 <= k <= 4).  W_h (Sec. 2.2:
  * element-wise [P^k]^d fields with continuous normal components) carries the
  * Brezzi-Douglas-Marini degrees of freedom:
  *   facet    int_F (v . n_F) q_l ds over an L2-orthonormal basis of P^k(F): n_F the outward

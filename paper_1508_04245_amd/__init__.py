@@ -193,7 +193,7 @@ class Mesh:
         return out
 
     def hdiv_size(self):
-        """(dim W_h, number of facets) of the H(div) space (2D: 1 <= k <= 6; 3D: 1 <= k <= 3)."""
+        """(dim W_h, number of facets) of the H(div) space (2D: 1 <= k <= 6; 3D: 1 <= k <= 4)."""
         n, nf = ctypes.c_int64(0), ctypes.c_int64(0)
         _check(lib().dg_hdiv_info(self._h, ctypes.byref(n), ctypes.byref(nf)))
         return n.value, nf.value

@@ -7,7 +7,7 @@
 //   c[i][m] = sum_a (J / det J)_ia ref[a][m],   ref[a][m] = sum_j (P u_T)_j C_j[a][m],
 // and J / det J is the adjugate of J^-1, which the mesh already stores.  One lane per element;
 // the reference dual basis C (ndof x d x np doubles) and, in 3D, the six facet parameter
-// changes sit in LDS.  The transpose runs in two passes: every element writes the
+// changes sit in LDS (3D k = 4: read in place, the dual basis through scalar loads).  The transpose runs in two passes: every element writes the
 // contributions P^T (C^T G) of its local dofs (G = adj(J^-1)^T F), then every global dof adds
 // its one (interior, boundary facet) or two (interior facet) contributions in a fixed order,
 // so the result is deterministic and needs no atomics.
@@ -31,7 +31,35 @@ struct HShape {
   static constexpr int NI = ND - (D + 1) * NFD;
   static constexpr int NQ = D == 3 ? 6 * NFD * NFD : 0;  // facet parameter changes (3D)
   static constexpr int TAB = ND * ND + NQ;
+  // the tables sit in LDS when they fit in 64 KiB; else (3D k = 4) every lane reads the
+  // reference dual basis with wave-uniform addresses through scalar loads, and the facet
+  // parameter changes (per-lane addresses) from global memory
+  static constexpr bool LDS = TAB * 8 <= 65536;
 };
+
+typedef const double __attribute__((address_space(4)))* cdptr;
+
+// stage the tables into LDS (all threads of the block take part) or use them in place;
+// returns the table base for per-lane reads
+template <int D, int K>
+__device__ __forceinline__ const double* transfer_tables(const double* tab) {
+  using S = HShape<D, K>;
+  if constexpr (S::LDS) {
+    __shared__ double st[S::LDS ? S::TAB : 1];
+    for (int i = threadIdx.x; i < S::TAB; i += 256) st[i] = tab[i];
+    __syncthreads();
+    return st;
+  } else {
+    return tab;
+  }
+}
+
+// entry i of the reference dual basis, read with a wave-uniform index
+template <int D, int K>
+__device__ __forceinline__ double dual_entry(const double* st, const double* tab, int i) {
+  if constexpr (HShape<D, K>::LDS) return st[i];
+  else return ((cdptr)tab)[i];
+}
 
 // facet code of an element's local facet: global facet id, facet sign, 3D permutation code
 template <int D>
@@ -71,9 +99,7 @@ __global__ void __launch_bounds__(256) to_dg_kernel(int64_t E, int64_t nfd, cons
                                                     const int* hf, const double* jinv,
                                                     const double* tab, double* out) {
   using S = HShape<D, K>;
-  __shared__ double st[S::TAB];
-  for (int i = threadIdx.x; i < S::TAB; i += 256) st[i] = tab[i];
-  __syncthreads();
+  const double* st = transfer_tables<D, K>(tab);
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= E) return;
   double ref[D][S::NP];
@@ -85,7 +111,8 @@ __global__ void __launch_bounds__(256) to_dg_kernel(int64_t E, int64_t nfd, cons
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-      for (int m = 0; m < S::NP; ++m) ref[a][m] = fma(uj, st[(j * D + a) * S::NP + m], ref[a][m]);
+      for (int m = 0; m < S::NP; ++m)
+        ref[a][m] = fma(uj, dual_entry<D, K>(st, tab, (j * D + a) * S::NP + m), ref[a][m]);
   };
   // facet dofs in local form (reference dof order), then the interior dofs
 #pragma unroll
@@ -132,9 +159,7 @@ __global__ void __launch_bounds__(256) transpose_local_kernel(int64_t E, const d
                                                               const int* hf, const double* jinv,
                                                               const double* tab, double* loc) {
   using S = HShape<D, K>;
-  __shared__ double st[S::TAB];
-  for (int i = threadIdx.x; i < S::TAB; i += 256) st[i] = tab[i];
-  __syncthreads();
+  const double* st = transfer_tables<D, K>(tab);
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= E) return;
   double A[D][D];
@@ -160,7 +185,8 @@ __global__ void __launch_bounds__(256) transpose_local_kernel(int64_t E, const d
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-      for (int m = 0; m < S::NP; ++m) acc = fma(st[(j * D + a) * S::NP + m], G[a][m], acc);
+      for (int m = 0; m < S::NP; ++m)
+        acc = fma(dual_entry<D, K>(st, tab, (j * D + a) * S::NP + m), G[a][m], acc);
     return acc;
   };
 #pragma unroll
@@ -261,13 +287,13 @@ dg_status run_transpose(const dg_mesh* m, const double* F, double* out, hipStrea
   return DG_OK;
 }
 
-// degrees with kernels: 1..6 in 2D, 1..3 in 3D (the 3D tables fill the LDS beyond)
-bool hdiv_degree_ok(int dim, int k) { return k >= 1 && k <= (dim == 2 ? 6 : 3); }
+// degrees with kernels: 1..6 in 2D, 1..4 in 3D (the operator kernels' range)
+bool hdiv_degree_ok(int dim, int k) { return k >= 1 && k <= (dim == 2 ? 6 : 4); }
 
 dg_status prepare(const dg_mesh* m) {
   if (m->h.dim != 2 && m->h.dim != 3) return fail(DG_EINVAL, "the H(div) transfer needs dim 2 or 3");
   if (!hdiv_degree_ok(m->h.dim, m->h.k))
-    return fail(DG_EINVAL, "the H(div) transfer needs 1 <= k <= 6 (2D) or 1 <= k <= 3 (3D)");
+    return fail(DG_EINVAL, "the H(div) transfer needs 1 <= k <= 6 (2D) or 1 <= k <= 4 (3D)");
   dg_status st = dgi::ensure_device(m);
   if (st != DG_OK) return st;
   return ensure_hdiv(m);
@@ -281,7 +307,7 @@ dg_status dg_hdiv_info(const dg_mesh* m, int64_t* n_dof, int64_t* n_facet) {
   if (!m || !n_dof) return fail(DG_EINVAL, "null pointer");
   if (m->h.dim != 2 && m->h.dim != 3) return fail(DG_EINVAL, "the H(div) transfer needs dim 2 or 3");
   if (!hdiv_degree_ok(m->h.dim, m->h.k))
-    return fail(DG_EINVAL, "the H(div) transfer needs 1 <= k <= 6 (2D) or 1 <= k <= 3 (3D)");
+    return fail(DG_EINVAL, "the H(div) transfer needs 1 <= k <= 6 (2D) or 1 <= k <= 4 (3D)");
   dghdiv::Host hd;
   std::string err;
   const int rc = dghdiv::build(m->h, hd, err);
@@ -294,7 +320,7 @@ dg_status dg_hdiv_info(const dg_mesh* m, int64_t* n_dof, int64_t* n_facet) {
 dg_status dg_hdiv_reference(int dim, int k, double* table_out) {
   if (!table_out) return fail(DG_EINVAL, "null pointer");
   if ((dim != 2 && dim != 3) || !hdiv_degree_ok(dim, k))
-    return fail(DG_EINVAL, "need dim 2 with k in 1..6 or dim 3 with k in 1..3");
+    return fail(DG_EINVAL, "need dim 2 with k in 1..6 or dim 3 with k in 1..4");
   std::vector<double> t;
   dghdiv::reference_dual(dim, k, t);
   std::memcpy(table_out, t.data(), t.size() * sizeof(double));
@@ -311,7 +337,8 @@ dg_status dg_transfer_to_dg(const dg_mesh* m, const double* u, double* w_out, vo
     switch (m->h.k) {
       case 1: return run_to_dg<3, 1>(m, u, w_out, s);
       case 2: return run_to_dg<3, 2>(m, u, w_out, s);
-      default: return run_to_dg<3, 3>(m, u, w_out, s);
+      case 3: return run_to_dg<3, 3>(m, u, w_out, s);
+      default: return run_to_dg<3, 4>(m, u, w_out, s);
     }
   }
   switch (m->h.k) {
@@ -335,7 +362,8 @@ dg_status dg_transfer_transpose(const dg_mesh* m, const double* f, double* g_out
     switch (m->h.k) {
       case 1: return run_transpose<3, 1>(m, f, g_out, s);
       case 2: return run_transpose<3, 2>(m, f, g_out, s);
-      default: return run_transpose<3, 3>(m, f, g_out, s);
+      case 3: return run_transpose<3, 3>(m, f, g_out, s);
+      default: return run_transpose<3, 4>(m, f, g_out, s);
     }
   }
   switch (m->h.k) {

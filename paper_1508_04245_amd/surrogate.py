@@ -1,6 +1,6 @@
 """Driver of the learned macro-step: data from the plain method, training, evaluation.
 
-All arithmetic runs in libdgconv.so (the plain SSP-RK3 substeps that generate and judge the
+All arithmetic runs in libdgconv.so (the plain SSP-RK3 substeps that generate and check the
 data, the feature gather, the BF16 network kernels, Adam, the macro-step with its defect check
 and fallback); this module only sequences calls and holds the data in device memory.
 

@@ -2,7 +2,7 @@
 I u (dg_transfer_to_dg) and I^T f (dg_transfer_transpose) on jittered, shuffled-frame and
 bounded 2D meshes with ragged last blocks, degrees 1..6, and on a 64x64x2 box; in 3D on
 jittered, shuffled-frame (every facet orientation) and bounded tetrahedral meshes, degrees
-1..3, and on an 8x8x8x6 box.
+1..4, and on an 8x8x8x6 box.
 Every test prints its case before touching the GPU.
 """
 import numpy as np
@@ -46,7 +46,7 @@ def mesh(kind, N, seed, dim=2):
 CASES = [(2, "jittered", 9, k) for k in (1, 2, 3)] + [(2, "shuffled", 7, k) for k in (4, 5, 6)] + \
         [(2, "bounded", 7, 2), (2, "bounded", 6, 4), (2, "box", 64, 4)] + \
         [(3, "jittered", 3, 1), (3, "shuffled", 3, 2), (3, "shuffled", 2, 3), (3, "bounded", 3, 3),
-         (3, "bounded", 2, 1), (3, "box", 8, 3)]
+         (3, "bounded", 2, 1), (3, "box", 8, 3), (3, "shuffled", 2, 4), (3, "bounded", 2, 4)]
 
 
 @pytest.mark.parametrize("dim,kind,N,k", CASES)

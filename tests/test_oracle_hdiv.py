@@ -36,7 +36,7 @@ MESHES_3D = ["bounded3", "jittered3", "shuffled3"]
 
 
 @pytest.mark.parametrize("name,k", [(n, k) for n in MESHES_2D for k in (1, 2, 3, 4)] +
-                         [(n, k) for n in MESHES_3D for k in (1, 2, 3)])
+                         [(n, k) for n in MESHES_3D for k in (1, 2, 3)] + [("shuffled3", 4)])
 def test_dof_duality(name, k):
     """The dof functionals, evaluated directly on the DG field I u, give back u."""
     m = MESHES[name]()
