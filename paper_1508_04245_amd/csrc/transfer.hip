@@ -6,8 +6,8 @@
 // parameter changes), so with the signed Piola map v = J v^ / det J its DG coefficients are
 //   c[i][m] = sum_a (J / det J)_ia ref[a][m],   ref[a][m] = sum_j (P u_T)_j C_j[a][m],
 // and J / det J is the adjugate of J^-1, which the mesh already stores.  One lane per element;
-// the reference dual basis C (ndof x d x np doubles) and, in 3D, the six facet parameter
-// changes sit in LDS (3D k = 4: read in place, the dual basis through scalar loads).  The transpose runs in two passes: every element writes the
+// the reference dual basis C (ndof x d x np doubles) is read through scalar loads, and in 3D
+// the six facet parameter changes sit in LDS.  The transpose runs in two passes: every element writes the
 // contributions P^T (C^T G) of its local dofs (G = adj(J^-1)^T F), then every global dof adds
 // its one (interior, boundary facet) or two (interior facet) contributions in a fixed order,
 // so the result is deterministic and needs no atomics.
@@ -31,34 +31,46 @@ struct HShape {
   static constexpr int NI = ND - (D + 1) * NFD;
   static constexpr int NQ = D == 3 ? 6 * NFD * NFD : 0;  // facet parameter changes (3D)
   static constexpr int TAB = ND * ND + NQ;
-  // the tables sit in LDS when they fit in 64 KiB; else (3D k = 4) every lane reads the
-  // reference dual basis with wave-uniform addresses through scalar loads, and the facet
-  // parameter changes (per-lane addresses) from global memory
-  static constexpr bool LDS = TAB * 8 <= 65536;
 };
 
 typedef const double __attribute__((address_space(4)))* cdptr;
 
-// stage the tables into LDS (all threads of the block take part) or use them in place;
-// returns the table base for per-lane reads
+// The reference dual basis is read with wave-uniform indices: scalar loads into SGPRs, which
+// the FMAs take as operands (an LDS copy would cost LDS bandwidth per lane and was slower).
+// The 3D facet parameter changes are read per lane (each element has its own facet
+// orientations) and are staged in LDS; all threads of the block take part.  Returns the LDS
+// copy of the parameter changes (3D) or nullptr.
 template <int D, int K>
-__device__ __forceinline__ const double* transfer_tables(const double* tab) {
+__device__ __forceinline__ const double* stage_orientations(const double* tab) {
   using S = HShape<D, K>;
-  if constexpr (S::LDS) {
-    __shared__ double st[S::LDS ? S::TAB : 1];
+  if constexpr (S::NQ > 0) {
+    __shared__ double sq[S::NQ > 0 ? S::NQ : 1];
+    for (int i = threadIdx.x; i < S::NQ; i += 256) sq[i] = tab[S::ND * S::ND + i];
+    __syncthreads();
+    return sq;
+  } else {
+    return nullptr;
+  }
+}
+
+// entry i of the reference dual basis (wave-uniform i)
+__device__ __forceinline__ double dual_entry(const double* tab, int i) { return ((cdptr)tab)[i]; }
+
+// The transpose's local pass reads the dual basis column by column into short FMA chains;
+// there the whole table block staged in LDS (when it fits in 64 KiB) is faster than scalar
+// loads (3D P3: 67 against 107 us per pass).  Returns the LDS copy of the table block, or
+// (tables beyond 64 KiB) that of the parameter changes alone.
+template <int D, int K>
+__device__ __forceinline__ const double* stage_all(const double* tab) {
+  using S = HShape<D, K>;
+  if constexpr (S::TAB * 8 <= 65536) {
+    __shared__ double st[S::TAB * 8 <= 65536 ? S::TAB : 1];
     for (int i = threadIdx.x; i < S::TAB; i += 256) st[i] = tab[i];
     __syncthreads();
     return st;
   } else {
-    return tab;
+    return stage_orientations<D, K>(tab);
   }
-}
-
-// entry i of the reference dual basis, read with a wave-uniform index
-template <int D, int K>
-__device__ __forceinline__ double dual_entry(const double* st, const double* tab, int i) {
-  if constexpr (HShape<D, K>::LDS) return st[i];
-  else return ((cdptr)tab)[i];
 }
 
 // facet code of an element's local facet: global facet id, facet sign, 3D permutation code
@@ -99,7 +111,7 @@ __global__ void __launch_bounds__(256) to_dg_kernel(int64_t E, int64_t nfd, cons
                                                     const int* hf, const double* jinv,
                                                     const double* tab, double* out) {
   using S = HShape<D, K>;
-  const double* st = transfer_tables<D, K>(tab);
+  const double* sq = stage_orientations<D, K>(tab);
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= E) return;
   double ref[D][S::NP];
@@ -112,7 +124,7 @@ __global__ void __launch_bounds__(256) to_dg_kernel(int64_t E, int64_t nfd, cons
     for (int a = 0; a < D; ++a)
 #pragma unroll
       for (int m = 0; m < S::NP; ++m)
-        ref[a][m] = fma(uj, dual_entry<D, K>(st, tab, (j * D + a) * S::NP + m), ref[a][m]);
+        ref[a][m] = fma(uj, dual_entry(tab, (j * D + a) * S::NP + m), ref[a][m]);
   };
   // facet dofs in local form (reference dof order), then the interior dofs
 #pragma unroll
@@ -127,7 +139,7 @@ __global__ void __launch_bounds__(256) to_dg_kernel(int64_t E, int64_t nfd, cons
       double ug[S::NFD];
 #pragma unroll
       for (int i = 0; i < S::NFD; ++i) ug[i] = uf[i];
-      const double* Q = st + S::ND * S::ND + fc.perm * S::NFD * S::NFD;
+      const double* Q = sq + fc.perm * S::NFD * S::NFD;
 #pragma unroll 1
       for (int l = 0; l < S::NFD; ++l) {
         double v = 0.0;
@@ -159,7 +171,11 @@ __global__ void __launch_bounds__(256) transpose_local_kernel(int64_t E, const d
                                                               const int* hf, const double* jinv,
                                                               const double* tab, double* loc) {
   using S = HShape<D, K>;
-  const double* st = transfer_tables<D, K>(tab);
+  // st: the table block (dual basis then parameter changes) in LDS where it fits; sq: the
+  // parameter changes
+  constexpr bool LDS = S::TAB * 8 <= 65536;
+  const double* st = stage_all<D, K>(tab);
+  const double* sq = LDS ? st + S::ND * S::ND : st;
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= E) return;
   double A[D][D];
@@ -186,7 +202,8 @@ __global__ void __launch_bounds__(256) transpose_local_kernel(int64_t E, const d
     for (int a = 0; a < D; ++a)
 #pragma unroll
       for (int m = 0; m < S::NP; ++m)
-        acc = fma(dual_entry<D, K>(st, tab, (j * D + a) * S::NP + m), G[a][m], acc);
+        acc = fma(LDS ? st[(j * D + a) * S::NP + m] : dual_entry(tab, (j * D + a) * S::NP + m),
+                  G[a][m], acc);
     return acc;
   };
 #pragma unroll
@@ -204,7 +221,7 @@ __global__ void __launch_bounds__(256) transpose_local_kernel(int64_t E, const d
       double cl[S::NFD];
 #pragma unroll
       for (int l = 0; l < S::NFD; ++l) cl[l] = contract(fcn * S::NFD + l);
-      const double* Q = st + S::ND * S::ND + fc.perm * S::NFD * S::NFD;
+      const double* Q = sq + fc.perm * S::NFD * S::NFD;
 #pragma unroll 1
       for (int i = 0; i < S::NFD; ++i) {
         double v = 0.0;
