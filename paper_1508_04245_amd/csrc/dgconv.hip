@@ -158,7 +158,7 @@ hipError_t launch_maxvel(const dg_mesh* m, const double* a, hipStream_t s) {
 template <int D, int K, typename T>
 constexpr int default_tab_src() {
   if (!dgk::tables_in_lds<D, K, T>()) return dgk::SM_ALL;
-  if (D == 2 && K == 4 && sizeof(T) == 8) return 21;
+  if (D == 2 && K == 4 && sizeof(T) == 8) return 22;
   return 0;
 }
 
@@ -195,13 +195,16 @@ hipError_t launch_conv_dk(const dg_mesh* m, const dgk::ConvArgs<T>& a, hipStream
     return hipGetLastError();
   }
   // DGCONV_TABLES may pick another split for the FP64 self kernel: every table in LDS (0),
-  // every table through scalar loads (31), or the 2D P4 default (21)
+  // every table through scalar loads (31), the 2D P4 default (22: basis values and
+  // neighbour traces in LDS, the rest through scalar loads), or gradients and neighbour
+  // traces in LDS (21)
   const int src = m->tab_src < 0 || !dgk::tables_in_lds<D, K, T>() ? kDef : m->tab_src;
   if constexpr (dgk::tables_in_lds<D, K, T>() && SELF && sizeof(T) == 8) {
     if (src != kDef) {
       switch (src) {
         case 0: launch_conv_sm<D, K, T, SELF, 0>(a, grid, s); return hipGetLastError();
         case 21: launch_conv_sm<D, K, T, SELF, 21>(a, grid, s); return hipGetLastError();
+        case 22: launch_conv_sm<D, K, T, SELF, 22>(a, grid, s); return hipGetLastError();
         case dgk::SM_ALL:
           launch_conv_sm<D, K, T, SELF, dgk::SM_ALL>(a, grid, s);
           return hipGetLastError();
