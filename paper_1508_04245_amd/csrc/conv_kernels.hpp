@@ -110,7 +110,31 @@ enum { TB_BV = 0, TB_DV = 1, TB_TRO = 2, TB_TRN = 3, TB_LF = 4 };
 constexpr int kBoundaryTable = 0x7fff;
 constexpr int SM_ALL = 31;
 
-template <int SM, typename T>
+// [lo, hi): the part of the table block staged in LDS for source mask SM (the staged tables
+// in block order; both trace tables share one range)
+template <int D, int K, int SM>
+constexpr int staged_lo() {
+  using S = Shape<D, K>;
+  const bool tr = !((SM >> TB_TRO) & 1) || !((SM >> TB_TRN) & 1);
+  return !((SM >> TB_BV) & 1) ? S::OFF_BV : !((SM >> TB_DV) & 1) ? S::OFF_DV
+         : tr ? S::OFF_TR : !((SM >> TB_LF) & 1) ? S::OFF_LF : 0;
+}
+template <int D, int K, int SM>
+constexpr int staged_hi() {
+  using S = Shape<D, K>;
+  const bool tr = !((SM >> TB_TRO) & 1) || !((SM >> TB_TRN) & 1);
+  return !((SM >> TB_LF) & 1) ? S::TOTAL : tr ? S::OFF_LF : !((SM >> TB_DV) & 1) ? S::OFF_TR
+         : !((SM >> TB_BV) & 1) ? S::OFF_DV : 0;
+}
+
+// the tables mask SM stages fit in 64 KiB of LDS
+template <int D, int K, typename T, int SM>
+constexpr bool staged_fits() {
+  return (size_t)(staged_hi<D, K, SM>() - staged_lo<D, K, SM>()) * sizeof(T) <= 65536;
+}
+
+// LO: table index of the first staged value (the LDS copy holds [LO, hi) only)
+template <int SM, typename T, int LO = 0>
 struct Tabs {
   typedef const T __attribute__((address_space(4)))* cptr;
   const T* l;
@@ -118,7 +142,7 @@ struct Tabs {
   template <int ID>
   __device__ __forceinline__ T get(int i) const {
     if constexpr ((SM >> ID) & 1) return c[i];
-    else return l[i];
+    else return l[i - LO];
   }
 };
 
@@ -126,13 +150,14 @@ struct Tabs {
 template <int D, int K, int SM, typename T>
 __device__ __forceinline__ void stage_tables(T* stab, const T* tab) {
   using S = Shape<D, K>;
+  constexpr int LO = staged_lo<D, K, SM>();
   constexpr int beg[5] = {S::OFF_BV, S::OFF_DV, S::OFF_TR, S::OFF_TR, S::OFF_LF};
   constexpr int end[5] = {S::OFF_DV, S::OFF_TR, S::OFF_LF, S::OFF_LF, S::TOTAL};
 #pragma unroll
   for (int t = 0; t < 5; ++t) {
     if (t == TB_TRN && !((SM >> TB_TRO) & 1)) continue;  // same range as the own traces
     if ((SM >> t) & 1) continue;
-    for (int i = beg[t] + (int)threadIdx.x; i < end[t]; i += 256) stab[i] = tab[i];
+    for (int i = beg[t] + (int)threadIdx.x; i < end[t]; i += 256) stab[i - LO] = tab[i];
   }
 }
 
@@ -160,10 +185,12 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int tile = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
   if (stopped(A.stop)) return;  // uniform over the grid
-  Tabs<SM, T> tab;
-  tab.c = (typename Tabs<SM, T>::cptr)A.tab;
+  static_assert(SM == SM_ALL || staged_fits<D, K, T, SM>(), "staged tables exceed 64 KiB");
+  constexpr int LO = SM == SM_ALL ? 0 : staged_lo<D, K, SM>();
+  Tabs<SM, T, LO> tab;
+  tab.c = (typename Tabs<SM, T, LO>::cptr)A.tab;
   if constexpr (SM != SM_ALL) {
-    __shared__ T stab[S::TOTAL];
+    __shared__ T stab[staged_hi<D, K, SM>() - LO];
     stage_tables<D, K, SM>(stab, A.tab);
     __syncthreads();
     tab.l = stab;

@@ -150,13 +150,17 @@ hipError_t launch_maxvel(const dg_mesh* m, const double* a, hipStream_t s) {
 }
 
 // default table sources of the VALU kernel (bit t of the mask: table t read through scalar
-// loads, else from LDS; t = basis values, gradients, own traces, neighbour traces, lifts).
-// Tables too large for LDS all come through scalar loads.  For 2D P4 the basis values, own
-// traces and lifts through scalar loads halve the LDS reads per wave (measured on MI355X,
-// 2D 256x256x2 P4: 51.5 us per launch against 57.6 us with every table in LDS); smaller
-// elements keep every table in LDS.
-template <int D, int K, typename T>
+// loads, else from LDS; t = basis values, gradients, own traces, neighbour traces, lifts),
+// from sweeps of the masks on MI355X.  2D P4: basis values and neighbour traces in LDS, the
+// rest through scalar loads (mask 22: 48.3 us per launch on 256x256x2 triangles, against
+// 49.4 for 21, 57.6 with every table in LDS and 88 with none).  Smaller elements keep every
+// table in LDS; other tables too large for LDS all come through scalar loads.
+template <int D, int K, typename T, bool SELF = true, bool BND = false>
 constexpr int default_tab_src() {
+  // 3D P2 (70 KiB of tables): basis values and gradients in LDS, traces and lifts through
+  // scalar loads, for the FP64 self kernel (753 against 799 us per launch with every table
+  // through scalar loads); the frozen and boundary variants keep scalar loads
+  if (D == 3 && K == 2 && sizeof(T) == 8 && SELF && !BND) return 28;
   if (!dgk::tables_in_lds<D, K, T>()) return dgk::SM_ALL;
   if (D == 2 && K == 4 && sizeof(T) == 8) return 22;
   return 0;
@@ -177,7 +181,7 @@ constexpr int lane_tab_src() {
 
 template <int D, int K, typename T, bool SELF>
 hipError_t launch_conv_dk(const dg_mesh* m, const dgk::ConvArgs<T>& a, hipStream_t s) {
-  constexpr int kDef = default_tab_src<D, K, T>();
+  constexpr int kDef = default_tab_src<D, K, T, SELF>();
   // the kernel's compile-time table layout must match the host tables it reads
   if ((size_t)dgk::Shape<D, K>::TOTAL != m->t.total || dgk::Shape<D, K>::NP != m->h.np)
     return hipErrorInvalidValue;
@@ -191,24 +195,26 @@ hipError_t launch_conv_dk(const dg_mesh* m, const dgk::ConvArgs<T>& a, hipStream
     return hipErrorInvalidValue;  // never chosen at mesh creation for such elements
   }
   if (m->h.nbf > 0) {  // meshes with boundary facets: the variant that handles them
-    launch_conv_sm<D, K, T, SELF, kDef, true>(a, grid, s);
+    launch_conv_sm<D, K, T, SELF, default_tab_src<D, K, T, SELF, true>(), true>(a, grid, s);
     return hipGetLastError();
   }
-  // DGCONV_TABLES may pick another split for the FP64 self kernel: every table in LDS (0),
-  // every table through scalar loads (31), the 2D P4 default (22: basis values and
-  // neighbour traces in LDS, the rest through scalar loads), or gradients and neighbour
-  // traces in LDS (21)
-  const int src = m->tab_src < 0 || !dgk::tables_in_lds<D, K, T>() ? kDef : m->tab_src;
-  if constexpr (dgk::tables_in_lds<D, K, T>() && SELF && sizeof(T) == 8) {
-    if (src != kDef) {
-      switch (src) {
-        case 0: launch_conv_sm<D, K, T, SELF, 0>(a, grid, s); return hipGetLastError();
-        case 21: launch_conv_sm<D, K, T, SELF, 21>(a, grid, s); return hipGetLastError();
-        case 22: launch_conv_sm<D, K, T, SELF, 22>(a, grid, s); return hipGetLastError();
-        case dgk::SM_ALL:
-          launch_conv_sm<D, K, T, SELF, dgk::SM_ALL>(a, grid, s);
-          return hipGetLastError();
-        default: return hipErrorInvalidValue;
+  // DGCONV_TABLES may pick another split for the FP64 self kernel: every table through
+  // scalar loads (31) and, where the whole block fits in LDS, every table in LDS (0), 21
+  // (gradients and neighbour traces in LDS) or 22; other values keep the default
+  if constexpr (SELF && sizeof(T) == 8) {
+    const int src = m->tab_src;
+    if (src >= 0 && src != kDef) {
+      if (src == dgk::SM_ALL) {
+        launch_conv_sm<D, K, T, SELF, dgk::SM_ALL>(a, grid, s);
+        return hipGetLastError();
+      }
+      if constexpr (dgk::tables_in_lds<D, K, T>()) {
+        switch (src) {
+          case 0: launch_conv_sm<D, K, T, SELF, 0>(a, grid, s); return hipGetLastError();
+          case 21: launch_conv_sm<D, K, T, SELF, 21>(a, grid, s); return hipGetLastError();
+          case 22: launch_conv_sm<D, K, T, SELF, 22>(a, grid, s); return hipGetLastError();
+          default: break;
+        }
       }
     }
   }
