@@ -161,6 +161,10 @@ constexpr int default_tab_src() {
   // scalar loads, for the FP64 self kernel (753 against 799 us per launch with every table
   // through scalar loads); the frozen and boundary variants keep scalar loads
   if (D == 3 && K == 2 && sizeof(T) == 8 && SELF && !BND) return 28;
+  // FP32 self kernels: 3D P2 with basis values and neighbour traces in LDS (410 against 473
+  // us with every table in LDS); 2D P4 with the lifts through scalar loads (35.0 against 36.2)
+  if (D == 3 && K == 2 && sizeof(T) == 4 && SELF && !BND) return 22;
+  if (D == 2 && K == 4 && sizeof(T) == 4 && SELF && !BND) return 16;
   if (!dgk::tables_in_lds<D, K, T>()) return dgk::SM_ALL;
   if (D == 2 && K == 4 && sizeof(T) == 8) return 22;
   return 0;
