@@ -31,8 +31,8 @@ TRAFFIC_SOURCES = ("paper_1508_04245_amd/csrc/conv_kernels.hpp",
                    "paper_1508_04245_amd/csrc/mfma_kernels.hpp",
                    "paper_1508_04245_amd/csrc/dgconv.hip")
 MEASURED_TRAFFIC = {
-    ("c2", "fp64", "valu"): (114.6e6, "c6292fdabf20f553"),
-    ("c3", "fp64", "mfma"): (428.4e6, "c6292fdabf20f553"),
+    ("c2", "fp64", "valu"): (114.9e6, "f85d48a3f812b9c2"),
+    ("c3", "fp64", "mfma"): (428.4e6, "f85d48a3f812b9c2"),
 }
 
 

@@ -179,6 +179,9 @@ void launch_conv_sm(const dgk::ConvArgs<T>& a, dim3 grid, hipStream_t s) {
 // scalar loads when the whole set does not fit the 64 KiB a class-tiled kernel stages
 template <int D, int K, typename T>
 constexpr int lane_tab_src() {
+  // 2D P4 FP64: the weighted gradients through scalar loads (jittered 256x256x2: 51.4 against
+  // 52.3 us per launch with every table in LDS; the basis values too: 84 us)
+  if (D == 2 && K == 4 && sizeof(T) == 8) return 1 << dgk::TB_DV;
   return (size_t)dgk::Shape<D, K>::TOTAL * sizeof(T) <= 65536 ? 0
                                                               : (1 << dgk::TB_BV) | (1 << dgk::TB_DV);
 }
