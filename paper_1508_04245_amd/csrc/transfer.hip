@@ -5,12 +5,13 @@
 // On element T a W_h field is Piola(sum_j (P u_T)_j psi^_j), P the local map (facet signs and
 // parameter changes), so with the signed Piola map v = J v^ / det J its DG coefficients are
 //   c[i][m] = sum_a (J / det J)_ia ref[a][m],   ref[a][m] = sum_j (P u_T)_j C_j[a][m],
-// and J / det J is the adjugate of J^-1, which the mesh already stores.  One lane per element;
-// the reference dual basis C (ndof x d x np doubles) is read through scalar loads, and in 3D
-// the six facet parameter changes sit in LDS.  The transpose runs in two passes: every element writes the
-// contributions P^T (C^T G) of its local dofs (G = adj(J^-1)^T F), then every global dof adds
-// its one (interior, boundary facet) or two (interior facet) contributions in a fixed order,
-// so the result is deterministic and needs no atomics.
+// and J / det J is the adjugate of J^-1, which the mesh already stores.  One lane per element.
+// I reads the reference dual basis C (ndof x d x np doubles) through scalar loads; the local
+// pass of I^T reads it from LDS where the tables fit; the 3D facet parameter changes sit in
+// LDS.  The transpose runs in two passes: every element writes the contributions
+// P^T (C^T G) of its local dofs (G = adj(J^-1)^T F), then every global dof adds its one
+// (interior, boundary facet) or two (interior facet) contributions in a fixed order, so the
+// result is deterministic and needs no atomics.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
