@@ -6,6 +6,13 @@ div(w (x) w); initial field = L2 projection of the Taylor-Green field plus seede
 coefficient noise; dt = 0.1 h / (k^2 max|u|).  One step = one SSP-RK3 substep (three fused
 operator-plus-stage launches).  Inputs are resident in device memory when timing starts.
 
+The timed substeps run as one HIP graph (captured after the warm-up through torch's graph
+capture on the stream the library launches on), so the launches of the 3 K kernels are
+submitted at once; `--no-graph` times the eager launches instead.  Beside the headline the line
+carries the mixed variants on the same workload (the same K substeps from the same state:
+time per substep, final-state relative L2 error against FP64, the cheapest within 1e-6), the
+FP64 rate of the 3D 64^3 x 6 P2 workload, and the FP64 oracle on the host (all cores and one).
+
 Prints one JSON line.  `--gpus N` with N > 1 is not supported (this benchmark runs on one GPU).
 """
 import argparse
@@ -52,7 +59,7 @@ def kernel_label(cfg, precision, fp64_kernel):
     if precision == "fp64":
         kind = fp64_kernel or ("mfma" if NP >= 20 or (cfg["dim"], cfg["k"]) == (2, 3) else "valu")
     else:
-        kind = "valu" if precision == "fp32" else "mfma"
+        kind = "valu" if precision in ("fp32", "mixf32") else "mfma"
     name = "conv_kernel" if kind == "valu" else "mconv_kernel"
     return kind, "%s<%d,%d,%s,self>" % (name, cfg["dim"], cfg["k"], precision)
 
@@ -120,15 +127,33 @@ def make_state(dg, cfg, seed=0, mesh="box"):
     return m, w
 
 
+def _oracle_worker(sp, w, elems, n, barrier, out):
+    """One process of the all-cores oracle run: a warm application on its elements, then n
+    timed ones after every process is ready."""
+    sp.apply(w, elems=elems)
+    barrier.wait()
+    t0, c0 = time.perf_counter(), time.process_time()
+    for _ in range(n):
+        sp.apply(w, elems=elems)
+    out.put((time.perf_counter() - t0, time.process_time() - c0))
+
+
 def cpu_baseline(cfg, budget_s=30.0):
-    """The FP64 oracle, as it stands, on the same mesh: one untimed warm application, then
-    timed applications of the full operator until the budget is used; DOF-updates/s with one
-    SSP-RK3 substep = 3 applications."""
+    """The FP64 oracle, as it stands, on the same mesh, on the host cores of this machine.
+
+    One core: one untimed warm application, then timed applications of the full operator for
+    about budget_s / 2.  All cores: the same operator applied by P processes at once (P = the
+    CPUs this process may run on, at most 16), each taking a fixed contiguous share of the
+    elements through the oracle's own element selection, after a warm application; timed from
+    the moment all are ready to the last one's end, for about budget_s / 3.  DOF-updates/s with
+    one SSP-RK3 substep = 3 applications."""
+    import multiprocessing as mp
     from oracle.dg import Space
     from oracle.mesh import box_mesh
     from paper_1508_04245_amd import synth
     sp = Space(box_mesh(cfg["dim"], cfg["n"]), cfg["k"])
     w = synth.noise(sp.shape, seed=0, sd=1.0)
+    ndof = int(np.prod(sp.shape))
     sp.apply(w)
     t0, c0 = time.perf_counter(), time.process_time()
     n = 0
@@ -139,16 +164,38 @@ def cpu_baseline(cfg, budget_s=30.0):
             break
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
-    ndof = int(np.prod(sp.shape))
-    return {"value": ndof * n / 3.0 / wall, "unit": "DOF-updates/s",
-            "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
-            "sample": "%d full operator application(s) of the FP64 NumPy oracle on the same "
-                      "mesh after one warm call (%.1f s), scaled to SSP-RK3 substeps "
-                      "(3 applications each); %d logical CPUs visible"
-                      % (n, wall, len(os.sched_getaffinity(0)))}
+    one = {"value": ndof * n / 3.0 / wall, "unit": "DOF-updates/s",
+           "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
+           "sample": "%d full operator application(s) of the FP64 NumPy oracle on the same mesh "
+                     "after one warm call (%.1f s), scaled to SSP-RK3 substeps" % (n, wall)}
+    visible = len(os.sched_getaffinity(0))
+    P = max(1, min(16, visible))
+    per_apply = wall / n
+    reps = max(1, int(round(budget_s / 3 / (per_apply / P))))
+    ctx = mp.get_context("fork")
+    barrier, q = ctx.Barrier(P + 1), ctx.Queue()
+    parts = np.array_split(np.arange(sp.mesh.E), P)
+    procs = [ctx.Process(target=_oracle_worker, args=(sp, w, parts[i], reps, barrier, q))
+             for i in range(P)]
+    for pr in procs:
+        pr.start()
+    barrier.wait()
+    t0 = time.perf_counter()
+    res = [q.get() for _ in range(P)]
+    wall_all = time.perf_counter() - t0
+    for pr in procs:
+        pr.join()
+    cpu_all = sum(c for _, c in res)
+    return {"value": ndof * reps / 3.0 / wall_all, "unit": "DOF-updates/s",
+            "cores": max(1, int(round(cpu_all / wall_all))), "kind": "oracle",
+            "sample": "%d full operator applications of the FP64 NumPy oracle on the same mesh by "
+                      "%d processes at once (each a fixed share of the elements, after a warm "
+                      "call; %.1f s), scaled to SSP-RK3 substeps (3 applications each); %d "
+                      "logical CPUs visible" % (reps, P, wall_all, visible),
+            "processes": P, "one_core": one}
 
 
-STUDY_STEPS = {"c1": 100, "c2": 200, "c3": 40, "c4": 20, "c5": 200}
+STUDY_STEPS = {"c1": 100, "c2": 1000, "c3": 40, "c4": 200, "c5": 200}
 
 
 def precision_study(dg, cfgs, tol=1e-6):
@@ -158,7 +205,7 @@ def precision_study(dg, cfgs, tol=1e-6):
     import torch
     dev = torch.device("cuda", 0)
     variants = [("fp64", None), ("fp64", "valu"), ("fp64", "mfma"), ("fp32", None),
-                ("f16x2", None), ("bf16x3", None)]
+                ("mixf32", None), ("f16x2", None), ("bf16x3", None)]
     for name in cfgs:
         cfg = CONFIGS[name]
         steps = STUDY_STEPS[name]
@@ -300,6 +347,81 @@ def rows_study(dg, reps=50):
     emit("transfer I^T (V_h' -> W_h')", t, 2, (st3 + 2 * st3 + n_w3 * 8 + E3 * 88) / 2,
          {"n_hdiv": n_w3}, workload=wl3)
 
+def timed_substeps(m, w, dt, steps, work, prec, graph=True):
+    """Time `steps` SSP-RK3 substeps in place on w with HIP events on the current stream (the
+    one the library launches on).  graph: capture the substeps into one HIP graph first
+    (nothing runs during the capture) and time its replay.  Returns (GPU seconds, wall)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    g = None
+    if graph and steps > 0:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            m.rk_substeps(w, dt, steps, work=work, precision=prec)
+        torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    if g is not None:
+        g.replay()
+    else:
+        m.rk_substeps(w, dt, steps, work=work, precision=prec)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    del g
+    return ev0.elapsed_time(ev1) / 1e3, wall
+
+
+def mixed_variants(m, w_start, w_ref, dt, steps, t64, ty64, graph=True, tol=1e-6):
+    """The same substeps from the same state in every lower-precision variant: time per
+    substep, final-state relative L2 error against the FP64 result w_ref, speedup over FP64,
+    and the cheapest variant within tol."""
+    import torch
+    rows = []
+    for prec in ("fp32", "mixf32", "bf16x3", "f16x2"):
+        ty = torch.float32 if prec == "fp32" else torch.float64
+        w = w_start.to(ty).clone()
+        work = torch.empty((2,) + tuple(w.shape), dtype=ty, device=w.device)
+        m.rk_substeps(w.clone(), dt, 1, work=work, precision=prec)  # first-call setup
+        torch.cuda.synchronize()
+        t, _ = timed_substeps(m, w, dt, steps, work, prec, graph)
+        d = m.reduce("l2diff", w.to(torch.float64).contiguous(), w_ref)
+        err = float(d[0].item() / d[1].item())
+        rows.append({"precision": prec, "s_per_substep": t / steps, "rel_l2_vs_fp64": err,
+                     "speedup_vs_fp64": t64 / t})
+    ok = [r for r in rows if r["rel_l2_vs_fp64"] <= tol]
+    best = max(ok, key=lambda r: r["speedup_vs_fp64"]) if ok else None
+    return {"substeps": steps, "fp64_s_per_substep": t64 / steps, "tol": tol,
+            "variants": rows, "best_within_tol": best}
+
+
+def c4_rate(dg, graph=True, steps=10):
+    """FP64 rate of the 3D periodic 64^3 x 6 tetrahedra P2 workload (random Fourier field,
+    projected with 3 points per direction: the timing does not depend on the values)."""
+    import torch
+    from paper_1508_04245_amd import synth
+    cfg = CONFIGS["c4"]
+    m = dg.Mesh.box(cfg["dim"], cfg["n"], cfg["k"])
+    x = m.project_points(3)
+    w = torch.tensor(m.project(synth.FourierField(3, seed=0)(x), 3), device="cuda")
+    del x
+    umax = float(m.reduce("maxvel", w)[0].item())
+    dt = 0.1 / cfg["n"] / (cfg["k"] ** 2 * umax)
+    work = torch.empty((2,) + tuple(w.shape), dtype=torch.float64, device="cuda")
+    m.rk_substeps(w, dt, 2, work=work)
+    torch.cuda.synchronize()
+    t, _ = timed_substeps(m, w, dt, steps, work, "fp64", graph)
+    E = m.info["n_elem"]
+    per_launch = t / (3 * steps)
+    flops = alg_flops_per_elem(3, 2) * E
+    return {"workload": "3D periodic 64^3 x6 tetrahedra (1572864), vector P2, FP64",
+            "substeps": steps, "us_per_launch": per_launch * 1e6,
+            "dof_updates_per_s": m.info["n_dof"] * steps / t,
+            "roofline_frac": flops / per_launch / PEAK_FP64,
+            "hbm_equiv_GBps": alg_bytes_per_elem(3, 2) * E / per_launch / 1e9}
+
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -307,7 +429,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "f16x2", "bf16x3"])
+    ap.add_argument("--precision", default="fp64",
+                    choices=["fp64", "fp32", "mixf32", "f16x2", "bf16x3"])
     ap.add_argument("--fp64-kernel", default=None, choices=["valu", "mfma"],
                     help="FP64 operator kernel (default: the library's choice)")
     ap.add_argument("--n", type=int, default=None, help="override the mesh size (experiments)")
@@ -315,6 +438,10 @@ def main():
                     help="jittered: the box with moved vertices; shuffled: also arbitrary "
                          "element vertex orders (unstructured element frames)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager launches instead of one captured HIP graph")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the headline (no mixed variants, no 3D P2 rate)")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--rows", action="store_true",
                     help="time the rows beside the self-convection substeps (one JSON line each)")
@@ -367,14 +494,8 @@ def main():
     prec = args.precision
     m.rk_substeps(w, dt, args.warmup, work=work, precision=prec)
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    m.rk_substeps(w, dt, args.steps, work=work, precision=prec)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    w_start = w.clone()
+    gpu_s, wall = timed_substeps(m, w, dt, args.steps, work, prec, not args.no_graph)
     ndof = m.info["n_dof"]
     value = ndof * args.steps / gpu_s
     launches = 3 * args.steps
@@ -385,6 +506,7 @@ def main():
     peak = PEAK_FP64 if ty == torch.float64 else PEAK_FP32
     finite = torch.isfinite(w).all().item()
     # single operator applications (mode r = L(w), no Runge-Kutta stage), same stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     r_out = torch.empty_like(w)
     n_app = max(10, args.steps // 10)
     ev0.record(stream)
@@ -427,6 +549,12 @@ def main():
         "wall_s": wall,
         "final_state_finite": bool(finite),
     }
+    out["graph"] = not args.no_graph
+    if not args.no_extra and prec == "fp64" and not args.n and args.mesh == "box":
+        out["mixed"] = mixed_variants(m, w_start, w, dt, args.steps, gpu_s, ty,
+                                      not args.no_graph)
+        if args.config != "c4":
+            out["c4_fp64"] = c4_rate(dg, not args.no_graph)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
     print(json.dumps(out))

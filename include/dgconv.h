@@ -45,14 +45,20 @@ typedef enum {
   DG_EMESH = -6         /* degenerate element, unmatched or non-manifold facet */
 } dg_status;
 
-/* Arithmetic of the operator.  The state is FP64 except for DG_FP32 (FP32 state). */
+/* Arithmetic of the operator.  The state is FP64 except for DG_FP32 (FP32 state).  The
+ * mixed variants keep the solution state, the facet flux, the lifted facet sums and the
+ * Runge-Kutta stage updates in FP64 and run the basis contractions in lower precision. */
 typedef enum {
   DG_FP64 = 0,      /* everything in FP64 */
   DG_FP32 = 1,      /* FP32 state and arithmetic */
+  DG_MIX_F32 = 2,   /* FP64 state, flux, facet sums and RK; basis contractions (coefficients,
+                       tables, volume sums) in FP32 on the vector units */
   DG_MIX_BF16x3 = 4,/* FP64 state, facet fluxes and RK; basis contractions as 3-way split
                        BF16 products on the matrix cores with FP32 accumulation */
   DG_MIX_F16x2 = 5  /* as above with 2-way split FP16 products (per-element power-of-two
                        scaling) */
+  /* 3 (a 2-way BF16 split, 16 significant bits) is not provided: it cannot reach the 1e-6
+     relative error the mixed variants are compared at */
 } dg_precision;
 
 typedef struct dg_mesh dg_mesh; /* opaque; immutable after creation */
@@ -222,12 +228,21 @@ dg_status dg_transfer_to_dg(const dg_mesh* mesh, const double* u, double* w_out,
 dg_status dg_transfer_transpose(const dg_mesh* mesh, const double* f, double* g_out,
                                 void* stream);
 
-/* Reductions of FP64 states into out_dev (dev, doubles), deterministic:
- *   DG_RED_MAXVEL   out[0] = max over the volume quadrature points of |a(x)|
- *   DG_RED_ENERGY   out[0] = 1/2 int |a|^2 dx
- *   DG_RED_MOMENTUM out[0..dim-1] = int a dx
+/* Reductions of FP64 states into out_dev (dev, doubles), deterministic (fixed summation
+ * order, two passes over per-block partial results in a mesh-owned buffer):
+ *   DG_RED_MAXVEL   out[0] = max over the volume quadrature points of |a(x)| (the speed in
+ *                   the substep size)
+ *   DG_RED_ENERGY   out[0] = 1/2 int |a|^2 dx, the kinetic energy whose stability the upwind
+ *                   form gives (Sec. 2.3, eq. convstab; Sec. 2.5, the energy estimate of the
+ *                   semidiscrete formulation)
+ *   DG_RED_MOMENTUM out[0..dim-1] = int a dx (conserved by the single-valued upwind flux of
+ *                   Sec. 2.3 on a periodic mesh)
  *   DG_RED_L2DIFF   out[0] = ||a - b||_L2, out[1] = ||b||_L2
- *   DG_RED_NONFINITE out[0] = number of non-finite coefficients of a */
+ *   DG_RED_NONFINITE out[0] = number of non-finite coefficients of a
+ * a, b: dev FP64 states (b only for DG_RED_L2DIFF); out_dev: dev, at least dim doubles.
+ * Calls on one mesh share its partial-result buffer: concurrent calls on different streams
+ * must be serialised by the caller.  Errors: DG_EINVAL (null pointer, unknown what, L2DIFF
+ * without b). */
 enum { DG_RED_MAXVEL = 0, DG_RED_ENERGY = 1, DG_RED_MOMENTUM = 2, DG_RED_L2DIFF = 3,
        DG_RED_NONFINITE = 4 };
 dg_status dg_reduce(const dg_mesh* mesh, int what, const double* a, const double* b,
@@ -247,7 +262,9 @@ typedef struct dg_surrogate dg_surrogate;
 dg_status dg_surrogate_n_params(int64_t* n); /* 157460 */
 
 /* Create a network for this mesh (allocates device memory; parameters zero until loaded).
- * M: substeps one macro-step replaces.  DG_EUNSUPPORTED unless dim = 2 and k = 3. */
+ * M: substeps one macro-step replaces.  DG_EUNSUPPORTED unless dim = 2 and k = 3, and for a
+ * mesh with boundary facets (the inputs need a neighbour across every facet); both checked
+ * before any device work. */
 dg_status dg_surrogate_create(const dg_mesh* mesh, int M, dg_surrogate** out);
 void dg_surrogate_destroy(dg_surrogate* s);
 
@@ -277,13 +294,20 @@ dg_status dg_surrogate_train_step(dg_surrogate* s, const float* x, const float* 
                                   int64_t batch, float lr, float* loss_dev, void* stream);
 
 /* One macro-step of M substeps of size dt on the FP64 state w (dev, in place, self-
- * convection): candidate w~ = w + tau r(w) + sigma (s^3 tau^2 / h) net(...), tau = M dt,
- * accepted when its trapezoid defect
- * rho = ||w~ - w - (M dt / 2)(r(w) + r(w~))||_L2 / ||w~ - w||_L2 <= tol, else the M plain
- * SSP-RK3 substeps are taken from w.  Synchronises the stream (the decision is made on the
- * host); *accepted = 1 or 0, *rho_out = rho (may be NULL).  Uses workspace owned by s. */
+ * convection; the propagation problem of Sec. 3.2 with u := w): candidate
+ * w~ = w + tau r(w) + sigma (s^3 tau^2 / h) net(...), tau = M dt, accepted when its trapezoid
+ * defect rho = ||w~ - w - (M dt / 2)(r(w) + r(w~))||_L2 / ||w~ - w||_L2 <= tol (a NaN defect,
+ * from non-finite values, is never accepted; w~ = w gives 0 if r(w) + r(w~) = 0, else
+ * infinity), else the M plain SSP-RK3 substeps are taken from w.  The check costs two
+ * operator applications, less than one substep (three).
+ * work: dev, at least 3 FP64 states (w~, r(w), r(w~); the fallback substeps reuse the last
+ * two), or NULL for a buffer owned by s; it must not overlap w.  The network's batch buffers
+ * are owned by s, so calls on one surrogate must be serialised.  Synchronises the stream
+ * (the decision is made on the host); *accepted = 1 or 0, *rho_out = rho (may be NULL).
+ * Errors: DG_EINVAL (null or misaligned pointers, dt <= 0 or non-finite, a surrogate created
+ * for another mesh). */
 dg_status dg_macro_step(const dg_mesh* mesh, dg_surrogate* s, double* w, double dt, double tol,
-                        int* accepted, double* rho_out, void* stream);
+                        void* work, int* accepted, double* rho_out, void* stream);
 
 /* Learned initial guess for dg_richardson (the pseudo-time problem of Sec. 3.3,
  * v + tau (M^V)^-1 C^V(u) v = g):

@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdgconv.so")
 
-PREC = {"fp64": 0, "fp32": 1, "bf16x3": 4, "f16x2": 5}
+PREC = {"fp64": 0, "fp32": 1, "mixf32": 2, "bf16x3": 4, "f16x2": 5}
 RED = {"maxvel": 0, "energy": 1, "momentum": 2, "l2diff": 3, "nonfinite": 4}
 
 _lib = None
@@ -77,7 +77,7 @@ def lib():
         "dg_surrogate_forward": [P, P, I64, P, P],
         "dg_surrogate_grad": [P, P, P, I64, P, P, P],
         "dg_surrogate_train_step": [P, P, P, I64, ctypes.c_float, P, P],
-        "dg_macro_step": [P, P, P, D, D, P, P, P],
+        "dg_macro_step": [P, P, P, D, D, P, P, P, P],
         "dg_surrogate_warm_start": [P, P, P, P, D, P, P],
     }
     for name, args in sig.items():
@@ -367,14 +367,15 @@ class Surrogate:
                                              None if loss is None else _dev(loss), _stream(stream)))
         return loss
 
-    def macro_step(self, w, dt, tol, stream=None):
-        """One macro-step in place on w; returns (accepted, rho)."""
+    def macro_step(self, w, dt, tol, work=None, stream=None):
+        """One macro-step in place on w; returns (accepted, rho).  work: None (the surrogate's
+        buffer) or a dev FP64 tensor of at least 3 states."""
         import torch
         acc = ctypes.c_int()
         rho = ctypes.c_double()
         _check(lib().dg_macro_step(self.mesh._h, self._h, _dev(w, torch.float64), float(dt),
-                                   float(tol), ctypes.byref(acc), ctypes.byref(rho),
-                                   _stream(stream)))
+                                   float(tol), None if work is None else _dev(work, torch.float64),
+                                   ctypes.byref(acc), ctypes.byref(rho), _stream(stream)))
         return bool(acc.value), rho.value
 
     def warm_start(self, g, u, tau, out=None, stream=None):

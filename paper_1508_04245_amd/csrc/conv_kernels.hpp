@@ -19,6 +19,13 @@
 //            b = 1/2 (u^- + u^+) . (J^-T n^_f |F^_f|)   (= beta |F| / |det J|)
 //   r = R   (the orthonormal reference basis makes M_T = |det J| I, which cancels)
 // and, in the fused Runge-Kutta mode, out = a w0 + b (x + dt r) for the stage of SSP-RK3.
+//
+// Two arithmetic types: TS for the state, the facet flux, the facet sums and the update, TC for
+// the basis contractions (coefficients and tables as TC, products and the volume sums in TC).
+// TS = TC = double is the FP64 path and TS = TC = float the FP32 path; TS = double with
+// TC = float keeps the state, the flux, the lifted facet sums and the Runge-Kutta update in
+// FP64 around FP32 contractions (the volume sums reach FP64 once, when the volume term is
+// added to R).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -40,7 +47,7 @@ struct Shape {
   static constexpr int TOTAL = OFF_LF + NTAB * NFQ * NP;
 };
 
-template <typename T>
+template <typename T, typename TC = T>
 struct ConvArgs {
   const T* x;          // state the operator acts on (neighbour traces are read from it)
   const T* u;          // frozen convecting velocity, or nullptr (u := x)
@@ -49,7 +56,7 @@ struct ConvArgs {
   const T* u2;         // second velocity field or nullptr: u(s) = u + uth (u2 - u)
   const T* w0;         // Runge-Kutta base state (mode 1, a != 0)
   T* out;              // mode 0: r;  mode 1: a w0 + b (x + dt r)
-  const T* tab;        // reference tables (Shape offsets)
+  const TC* tab;       // reference tables (Shape offsets), in the contraction type
   const T* jinv;       // [E][D][D]
   const int* nbr;      // [E][D+1]
   const int* elem_list;// [ntiles*64], -1 padded
@@ -175,11 +182,14 @@ constexpr bool lane_tables_ok() {
          (size_t)Shape<D, K>::TOTAL * sizeof(T) <= 100 * 1024;
 }
 
-template <int D, int K, typename T, bool SELF, int SM, bool BND, bool LANE = false>
+template <int D, int K, typename TS, bool SELF, int SM, bool BND, bool LANE = false,
+          typename T = TS>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvArgs<T> A) {
+__attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvArgs<TS, T> A) {
+  // T: contraction type (coefficients, tables, volume sums); TS: state, flux, facet sums
   using S = Shape<D, K>;
   constexpr int NP = S::NP;
+  constexpr bool MIX = sizeof(TS) != sizeof(T);
   typedef const int __attribute__((address_space(4)))* ciptr;
   const int lane = threadIdx.x & 63;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -206,37 +216,46 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
   const int e = e_raw >= 0 ? e_raw : A.elem_list[tile * 64];  // padded lanes redo lane 0
   const ciptr ttab = (ciptr)A.type_tab;
 
-  T c[D][NP], uc[SELF ? 1 : D][SELF ? 1 : NP], R[D][NP], ji[D][D];
+  T c[D][NP], uc[SELF ? 1 : D][SELF ? 1 : NP], Rv[D][NP], jic[D][D];
+  TS ji[D][D];
   {
-    const T* __restrict__ p = A.x + (size_t)e * D * NP;
+    const TS* __restrict__ p = A.x + (size_t)e * D * NP;
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
-      for (int m = 0; m < NP; ++m) c[i][m] = p[i * NP + m];
+      for (int m = 0; m < NP; ++m) c[i][m] = (T)p[i * NP + m];
     if constexpr (!SELF) {
-      const T* __restrict__ pu = A.u + (size_t)e * D * NP;
+      const TS* __restrict__ pu = A.u + (size_t)e * D * NP;
+      TS uw[D][NP];
 #pragma unroll
       for (int i = 0; i < D; ++i)
 #pragma unroll
-        for (int m = 0; m < NP; ++m) uc[i][m] = pu[i * NP + m];
+        for (int m = 0; m < NP; ++m) uw[i][m] = pu[i * NP + m];
       if (A.u2) {
-        const T* __restrict__ pu2 = A.u2 + (size_t)e * D * NP;
+        const TS* __restrict__ pu2 = A.u2 + (size_t)e * D * NP;
 #pragma unroll
         for (int i = 0; i < D; ++i)
 #pragma unroll
-          for (int m = 0; m < NP; ++m) uc[i][m] = fma(A.uth, pu2[i * NP + m] - uc[i][m], uc[i][m]);
+          for (int m = 0; m < NP; ++m) uw[i][m] = fma(A.uth, pu2[i * NP + m] - uw[i][m], uw[i][m]);
       }
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int m = 0; m < NP; ++m) uc[i][m] = (T)uw[i][m];
     }
-    const T* __restrict__ pj = A.jinv + (size_t)e * D * D;
+    const TS* __restrict__ pj = A.jinv + (size_t)e * D * D;
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
-      for (int j = 0; j < D; ++j) ji[i][j] = pj[i * D + j];
+      for (int j = 0; j < D; ++j) {
+        ji[i][j] = pj[i * D + j];
+        jic[i][j] = (T)ji[i][j];
+      }
   }
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int m = 0; m < NP; ++m) R[i][m] = T(0);
+    for (int m = 0; m < NP; ++m) Rv[i][m] = T(0);
 
   // ---- volume term
 #pragma unroll 1
@@ -269,7 +288,7 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
     for (int a = 0; a < D; ++a) {
       T s = T(0);
 #pragma unroll
-      for (int j = 0; j < D; ++j) s = fma(ji[a][j], uq[j], s);
+      for (int j = 0; j < D; ++j) s = fma(jic[a][j], uq[j], s);
       uh[a] = s;
     }
 #pragma unroll
@@ -278,9 +297,15 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
 #pragma unroll
       for (int a = 0; a < D; ++a) P = fma(uh[a], tab.template get<TB_DV>(dq + m * D + a), P);
 #pragma unroll
-      for (int i = 0; i < D; ++i) R[i][m] = fma(wq[i], P, R[i][m]);
+      for (int i = 0; i < D; ++i) Rv[i][m] = fma(wq[i], P, Rv[i][m]);
     }
   }
+  // the volume term enters the state-type accumulator once
+  TS R[D][NP];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int m = 0; m < NP; ++m) R[i][m] = (TS)Rv[i][m];
 
   // ---- facet terms (pointwise upwind flux)
 #pragma unroll
@@ -302,29 +327,29 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
     // and the outer values replace the traces below
     const bool lbnd = LANE && BND && nbt == kBoundaryTable;
     const int ne = lbnd ? e : ne_raw;
-    T Nt[D];
+    TS Nt[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      T s = T(0);
+      TS s = TS(0);
 #pragma unroll
-      for (int a = 0; a < D; ++a) s = fma(ji[a][j], nref<D, T>(f, a), s);
+      for (int a = 0; a < D; ++a) s = fma(ji[a][j], nref<D, TS>(f, a), s);
       Nt[j] = s;
     }
-    // upwind flux at facet point q from the inner and outer traces, lifted into R
-    auto flux_lift = [&](int q, const T (&wm)[D], const T (&wp)[D], const T (&um)[D],
-                         const T (&up)[D]) {
-      T bb = T(0);
+    // upwind flux at facet point q from the inner and outer traces (state type), lifted into R
+    auto flux_lift = [&](int q, const TS (&wm)[D], const TS (&wp)[D], const TS (&um)[D],
+                         const TS (&up)[D]) {
+      TS bb = TS(0);
 #pragma unroll
       for (int j = 0; j < D; ++j) bb = fma(um[j] + up[j], Nt[j], bb);
       // b = bb / 2;  F = b (wm + wp) / 2 + |b| (wm - wp) / 2
-      const T hb = T(0.25) * bb;
-      const T ha = T(0.25) * fabs(bb);
-      T F[D];
+      const TS hb = TS(0.25) * bb;
+      const TS ha = TS(0.25) * fabs(bb);
+      TS F[D];
 #pragma unroll
       for (int i = 0; i < D; ++i) F[i] = hb * (wm[i] + wp[i]) + ha * (wm[i] - wp[i]);
 #pragma unroll
       for (int m = 0; m < NP; ++m) {
-        const T l = tab.template get<TB_LF>(lfo + q * NP + m);
+        const TS l = (TS)tab.template get<TB_LF>(lfo + q * NP + m);
 #pragma unroll
         for (int i = 0; i < D; ++i) R[i][m] = fma(-l, F[i], R[i][m]);
       }
@@ -334,27 +359,29 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
       // have boundary facets): the outer values are the given boundary data at the facet
       // points, [boundary facet][point][component]
       const size_t bf = (size_t)(-1 - ne_raw);
-      const T* __restrict__ pb = A.wb + bf * S::NFQ * D;
-      const T* __restrict__ pub = SELF ? pb : A.ub + bf * S::NFQ * D;
+      const TS* __restrict__ pb = A.wb + bf * S::NFQ * D;
+      const TS* __restrict__ pub = SELF ? pb : A.ub + bf * S::NFQ * D;
 #pragma unroll 1
       for (int q = 0; q < S::NFQ; ++q) {
-        T wm[D], wp[D], um[D], up[D];
+        T am[D], aum[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) { wm[i] = T(0); um[i] = T(0); }
+        for (int i = 0; i < D; ++i) { am[i] = T(0); aum[i] = T(0); }
 #pragma unroll
         for (int m = 0; m < NP; ++m) {
           const T to = tab.template get<TB_TRO>(tro + q * NP + m);
 #pragma unroll
           for (int i = 0; i < D; ++i) {
-            wm[i] = fma(to, c[i][m], wm[i]);
-            if constexpr (!SELF) um[i] = fma(to, uc[i][m], um[i]);
+            am[i] = fma(to, c[i][m], am[i]);
+            if constexpr (!SELF) aum[i] = fma(to, uc[i][m], aum[i]);
           }
         }
+        TS wm[D], wp[D], um[D], up[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
+          wm[i] = (TS)am[i];
+          um[i] = SELF ? wm[i] : (TS)aum[i];
           wp[i] = pb[q * D + i];
           up[i] = pub[q * D + i];
-          if constexpr (SELF) um[i] = wm[i];
         }
         flux_lift(q, wm, wp, um, up);
       }
@@ -364,57 +391,68 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
     const size_t lbf = lbnd ? (size_t)(-1 - ne_raw) : 0;
     T cn[D][NP], un[SELF ? 1 : D][SELF ? 1 : NP];
     {
-      const T* __restrict__ p = A.x + (size_t)ne * D * NP;
+      const TS* __restrict__ p = A.x + (size_t)ne * D * NP;
 #pragma unroll
       for (int i = 0; i < D; ++i)
 #pragma unroll
-        for (int m = 0; m < NP; ++m) cn[i][m] = p[i * NP + m];
+        for (int m = 0; m < NP; ++m) cn[i][m] = (T)p[i * NP + m];
       if constexpr (!SELF) {
-        const T* __restrict__ pu = A.u + (size_t)ne * D * NP;
+        const TS* __restrict__ pu = A.u + (size_t)ne * D * NP;
+        TS uw[D][NP];
 #pragma unroll
         for (int i = 0; i < D; ++i)
 #pragma unroll
-          for (int m = 0; m < NP; ++m) un[i][m] = pu[i * NP + m];
+          for (int m = 0; m < NP; ++m) uw[i][m] = pu[i * NP + m];
         if (A.u2) {
-          const T* __restrict__ pu2 = A.u2 + (size_t)ne * D * NP;
+          const TS* __restrict__ pu2 = A.u2 + (size_t)ne * D * NP;
 #pragma unroll
           for (int i = 0; i < D; ++i)
 #pragma unroll
-            for (int m = 0; m < NP; ++m) un[i][m] = fma(A.uth, pu2[i * NP + m] - un[i][m], un[i][m]);
+            for (int m = 0; m < NP; ++m) uw[i][m] = fma(A.uth, pu2[i * NP + m] - uw[i][m], uw[i][m]);
         }
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int m = 0; m < NP; ++m) un[i][m] = (T)uw[i][m];
       }
     }
 #pragma unroll 1
     for (int q = 0; q < S::NFQ; ++q) {
-      T wm[D], wp[D], um[D], up[D];
+      T am[D], ap[D];
 #pragma unroll
-      for (int i = 0; i < D; ++i) { wm[i] = T(0); wp[i] = T(0); }
+      for (int i = 0; i < D; ++i) { am[i] = T(0); ap[i] = T(0); }
 #pragma unroll
       for (int m = 0; m < NP; ++m) {
         const T to = tab.template get<TB_TRO>(tro + q * NP + m);
         const T tn = tab.template get<TB_TRN>(trn + q * NP + m);
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-          wm[i] = fma(to, c[i][m], wm[i]);
-          wp[i] = fma(tn, cn[i][m], wp[i]);
+          am[i] = fma(to, c[i][m], am[i]);
+          ap[i] = fma(tn, cn[i][m], ap[i]);
         }
       }
+      TS wm[D], wp[D], um[D], up[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) { wm[i] = (TS)am[i]; wp[i] = (TS)ap[i]; }
       if constexpr (SELF) {
 #pragma unroll
         for (int i = 0; i < D; ++i) { um[i] = wm[i]; up[i] = wp[i]; }
       } else {
+        T aum[D], aup[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) { um[i] = T(0); up[i] = T(0); }
+        for (int i = 0; i < D; ++i) { aum[i] = T(0); aup[i] = T(0); }
 #pragma unroll
         for (int m = 0; m < NP; ++m) {
           const T to = tab.template get<TB_TRO>(tro + q * NP + m);
           const T tn = tab.template get<TB_TRN>(trn + q * NP + m);
 #pragma unroll
           for (int i = 0; i < D; ++i) {
-            um[i] = fma(to, uc[i][m], um[i]);
-            up[i] = fma(tn, un[i][m], up[i]);
+            aum[i] = fma(to, uc[i][m], aum[i]);
+            aup[i] = fma(tn, un[i][m], aup[i]);
           }
         }
+#pragma unroll
+        for (int i = 0; i < D; ++i) { um[i] = (TS)aum[i]; up[i] = (TS)aup[i]; }
       }
       if constexpr (LANE && BND) {
         if (lbnd) {
@@ -429,11 +467,26 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
     }
   }
 
-  T* o = A.out + (size_t)e * D * NP;
+  // the state the update starts from, in the state type (the contraction copy is rounded when
+  // the types differ, so the state is read again)
+  TS xs[D][NP];
+  if constexpr (MIX) {
+    const TS* __restrict__ p = A.x + (size_t)e * D * NP;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int m = 0; m < NP; ++m) xs[i][m] = p[i * NP + m];
+  } else {
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int m = 0; m < NP; ++m) xs[i][m] = (TS)c[i][m];
+  }
+  TS* o = A.out + (size_t)e * D * NP;
   if (A.mode == 2) {
     // every lane takes part in the wave sum; padded lanes store nothing and add zero
-    const T* pg = A.w0 + (size_t)e * D * NP;
-    T gv[D][NP];
+    const TS* pg = A.w0 + (size_t)e * D * NP;
+    TS gv[D][NP];
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -443,8 +496,8 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
     for (int i = 0; i < D; ++i)
 #pragma unroll
       for (int m = 0; m < NP; ++m) {
-        const T res = fma(A.tau, R[i][m], gv[i][m] - c[i][m]);
-        if (e_raw >= 0) o[i * NP + m] = fma(A.ds, res, c[i][m]);
+        const TS res = fma(A.tau, R[i][m], gv[i][m] - xs[i][m]);
+        if (e_raw >= 0) o[i * NP + m] = fma(A.ds, res, xs[i][m]);
         acc = fma((double)res, (double)res, acc);
       }
     acc = wave_sum(e_raw >= 0 ? acc * A.absdet[e] : 0.0);
@@ -458,12 +511,12 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
 #pragma unroll
       for (int m = 0; m < NP; ++m) o[i * NP + m] = R[i][m];
   } else {
-    const T a = A.a, b = A.b, dt = A.dt;
-    if (a != T(0)) {
+    const TS a = A.a, b = A.b, dt = A.dt;
+    if (a != TS(0)) {
       // all loads of w0 before any store: out may be w0 itself (in-place last stage), and
       // back-to-back stores let whole cache lines complete in L2 before eviction
-      const T* pw = A.w0 + (size_t)e * D * NP;
-      T w0v[D][NP];
+      const TS* pw = A.w0 + (size_t)e * D * NP;
+      TS w0v[D][NP];
 #pragma unroll
       for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -473,12 +526,12 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
       for (int i = 0; i < D; ++i)
 #pragma unroll
         for (int m = 0; m < NP; ++m)
-          o[i * NP + m] = fma(a, w0v[i][m], b * fma(dt, R[i][m], c[i][m]));
+          o[i * NP + m] = fma(a, w0v[i][m], b * fma(dt, R[i][m], xs[i][m]));
     } else {
 #pragma unroll
       for (int i = 0; i < D; ++i)
 #pragma unroll
-        for (int m = 0; m < NP; ++m) o[i * NP + m] = b * fma(dt, R[i][m], c[i][m]);
+        for (int m = 0; m < NP; ++m) o[i * NP + m] = b * fma(dt, R[i][m], xs[i][m]);
     }
   }
 }

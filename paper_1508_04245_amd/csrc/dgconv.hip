@@ -170,9 +170,13 @@ constexpr int default_tab_src() {
   return 0;
 }
 
-template <int D, int K, typename T, bool SELF, int SM, bool BND = false, bool LANE = false>
-void launch_conv_sm(const dgk::ConvArgs<T>& a, dim3 grid, hipStream_t s) {
-  hipLaunchKernelGGL((dgk::conv_kernel<D, K, T, SELF, SM, BND, LANE>), grid, dim3(256), 0, s, a);
+// TS: state type; TC: contraction type (TS = double, TC = float: FP32 contractions around an
+// FP64 state, flux, facet sums and update)
+template <int D, int K, typename TS, bool SELF, int SM, bool BND = false, bool LANE = false,
+          typename TC = TS>
+void launch_conv_sm(const dgk::ConvArgs<TS, TC>& a, dim3 grid, hipStream_t s) {
+  hipLaunchKernelGGL((dgk::conv_kernel<D, K, TS, SELF, SM, BND, LANE, TC>), grid, dim3(256), 0,
+                     s, a);
 }
 
 // per-lane table mode: the facet tables must come from LDS; the volume tables go through
@@ -186,8 +190,9 @@ constexpr int lane_tab_src() {
                                                               : (1 << dgk::TB_BV) | (1 << dgk::TB_DV);
 }
 
-template <int D, int K, typename T, bool SELF>
-hipError_t launch_conv_dk(const dg_mesh* m, const dgk::ConvArgs<T>& a, hipStream_t s) {
+template <int D, int K, typename TS, typename T, bool SELF>
+hipError_t launch_conv_dk(const dg_mesh* m, const dgk::ConvArgs<TS, T>& a, hipStream_t s) {
+  // table sources follow the contraction type (the tables are stored in it)
   constexpr int kDef = default_tab_src<D, K, T, SELF>();
   // the kernel's compile-time table layout must match the host tables it reads
   if ((size_t)dgk::Shape<D, K>::TOTAL != m->t.total || dgk::Shape<D, K>::NP != m->h.np)
@@ -196,19 +201,20 @@ hipError_t launch_conv_dk(const dg_mesh* m, const dgk::ConvArgs<T>& a, hipStream
   const dim3 grid((m->h.ntiles + 3) / 4);
   if (m->h.lane_tables) {
     if constexpr (dgk::lane_tables_ok<D, K, T>()) {
-      launch_conv_sm<D, K, T, SELF, lane_tab_src<D, K, T>(), true, true>(a, grid, s);
+      launch_conv_sm<D, K, TS, SELF, lane_tab_src<D, K, T>(), true, true, T>(a, grid, s);
       return hipGetLastError();
     }
     return hipErrorInvalidValue;  // never chosen at mesh creation for such elements
   }
   if (m->h.nbf > 0) {  // meshes with boundary facets: the variant that handles them
-    launch_conv_sm<D, K, T, SELF, default_tab_src<D, K, T, SELF, true>(), true>(a, grid, s);
+    launch_conv_sm<D, K, TS, SELF, default_tab_src<D, K, T, SELF, true>(), true, false, T>(
+        a, grid, s);
     return hipGetLastError();
   }
   // DGCONV_TABLES may pick another split for the FP64 self kernel: every table through
   // scalar loads (31) and, where the whole block fits in LDS, every table in LDS (0), 21
   // (gradients and neighbour traces in LDS) or 22; other values keep the default
-  if constexpr (SELF && sizeof(T) == 8) {
+  if constexpr (SELF && sizeof(T) == 8 && sizeof(TS) == 8) {
     const int src = m->tab_src;
     if (src >= 0 && src != kDef) {
       if (src == dgk::SM_ALL) {
@@ -225,36 +231,33 @@ hipError_t launch_conv_dk(const dg_mesh* m, const dgk::ConvArgs<T>& a, hipStream
       }
     }
   }
-  launch_conv_sm<D, K, T, SELF, kDef>(a, grid, s);
+  launch_conv_sm<D, K, TS, SELF, kDef, false, false, T>(a, grid, s);
   return hipGetLastError();
 }
 
-template <typename T, bool SELF>
-hipError_t launch_conv(const dg_mesh* m, const dgk::ConvArgs<T>& a, hipStream_t s) {
+template <typename TS, typename TC, bool SELF>
+hipError_t launch_conv(const dg_mesh* m, const dgk::ConvArgs<TS, TC>& a, hipStream_t s) {
   const int d = m->h.dim, k = m->h.k;
 #define DG_CASE(D_, K_) \
-  if (d == D_ && k == K_) return launch_conv_dk<D_, K_, T, SELF>(m, a, s);
+  if (d == D_ && k == K_) return launch_conv_dk<D_, K_, TS, TC, SELF>(m, a, s);
   DG_CASE(2, 0) DG_CASE(2, 1) DG_CASE(2, 2) DG_CASE(2, 3) DG_CASE(2, 4) DG_CASE(2, 5)
   DG_CASE(2, 6) DG_CASE(3, 0) DG_CASE(3, 1) DG_CASE(3, 2) DG_CASE(3, 3) DG_CASE(3, 4)
 #undef DG_CASE
   return hipErrorInvalidValue;
 }
 
-template <typename T>
-hipError_t launch_conv_any(const dg_mesh* m, const dgk::ConvArgs<T>& a, hipStream_t s) {
-  return a.u ? launch_conv<T, false>(m, a, s) : launch_conv<T, true>(m, a, s);
+template <typename TS, typename TC>
+hipError_t launch_conv_any(const dg_mesh* m, const dgk::ConvArgs<TS, TC>& a, hipStream_t s) {
+  return a.u ? launch_conv<TS, TC, false>(m, a, s) : launch_conv<TS, TC, true>(m, a, s);
 }
 
-template <typename T>
-dgk::ConvArgs<T> base_args(const dg_mesh* m) {
-  dgk::ConvArgs<T> a{};
-  if constexpr (sizeof(T) == 8) {
-    a.tab = m->d_tab;
-    a.jinv = m->d_jinv;
-  } else {
-    a.tab = m->d_tab_f;
-    a.jinv = m->d_jinv_f;
-  }
+template <typename TS, typename TC = TS>
+dgk::ConvArgs<TS, TC> base_args(const dg_mesh* m) {
+  dgk::ConvArgs<TS, TC> a{};
+  if constexpr (sizeof(TC) == 8) a.tab = m->d_tab;
+  else a.tab = m->d_tab_f;
+  if constexpr (sizeof(TS) == 8) a.jinv = m->d_jinv;
+  else a.jinv = m->d_jinv_f;
   a.nbr = m->d_nbr;
   a.elem_list = m->d_elem_list;
   a.tile_type = m->d_tile_type;
@@ -270,16 +273,16 @@ struct Bnd {
   const void* ub;
 };
 
-template <typename T>
+template <typename T, typename TC = T>
 dg_status run_apply(const dg_mesh* m, const void* w, const void* u, void* r, hipStream_t s,
                     const Bnd* bc = nullptr) {
-  auto a = base_args<T>(m);
+  auto a = base_args<T, TC>(m);
   a.x = (const T*)w;
   a.u = (const T*)u;
   if (bc) { a.wb = (const T*)bc->wb; a.ub = (const T*)bc->ub; }
   a.out = (T*)r;
   a.mode = 0;
-  HIP_TRY(launch_conv_any<T>(m, a, s));
+  HIP_TRY(launch_conv_any(m, a, s));
   return DG_OK;
 }
 
@@ -295,14 +298,14 @@ struct Extrap {
   }
 };
 
-template <typename T>
+template <typename T, typename TC = T>
 dg_status run_rk(const dg_mesh* m, void* w, double dt, int n, const void* u, void* work,
                  hipStream_t s, const Extrap* ex = nullptr, const Bnd* bc = nullptr) {
   const size_t n_state = (size_t)m->h.E * m->h.dim * m->h.np;
   T* w0 = (T*)w;
   T* w1 = (T*)work;
   T* w2 = w1 + n_state;
-  auto a = base_args<T>(m);
+  auto a = base_args<T, TC>(m);
   a.u = (const T*)u;
   a.u2 = ex ? (const T*)ex->ub : nullptr;
   if (bc) { a.wb = (const T*)bc->wb; a.ub = (const T*)bc->ub; }
@@ -311,13 +314,13 @@ dg_status run_rk(const dg_mesh* m, void* w, double dt, int n, const void* u, voi
   for (int it = 0; it < n; ++it) {
     a.x = w0; a.w0 = nullptr; a.out = w1; a.a = T(0); a.b = T(1);
     if (ex) a.uth = (T)ex->weight(it, dt, 0.0);
-    HIP_TRY(launch_conv_any<T>(m, a, s));
+    HIP_TRY(launch_conv_any(m, a, s));
     a.x = w1; a.w0 = w0; a.out = w2; a.a = T(0.75); a.b = T(0.25);
     if (ex) a.uth = (T)ex->weight(it, dt, 1.0);
-    HIP_TRY(launch_conv_any<T>(m, a, s));
+    HIP_TRY(launch_conv_any(m, a, s));
     a.x = w2; a.w0 = w0; a.out = w0; a.a = T(1.0 / 3.0); a.b = T(2.0 / 3.0);
     if (ex) a.uth = (T)ex->weight(it, dt, 0.5);
-    HIP_TRY(launch_conv_any<T>(m, a, s));
+    HIP_TRY(launch_conv_any(m, a, s));
   }
   return DG_OK;
 }
@@ -469,6 +472,11 @@ dgm::MArgs<double> mbase_args(const dg_mesh* m, int engine) {
   return a;
 }
 
+bool known_precision(dg_precision p) {
+  return p == DG_FP64 || p == DG_FP32 || p == DG_MIX_F32 || p == DG_MIX_F16x2 ||
+         p == DG_MIX_BF16x3;
+}
+
 // engine of a precision on the matrix-core path, or -1 for the VALU kernels
 int engine_of(const dg_mesh* m, dg_precision prec, bool frozen) {
   if (prec == DG_MIX_F16x2) return 1;
@@ -566,6 +574,18 @@ rich_check_kernel(int nparts, const double* __restrict__ partial, double rtol, i
 }
 
 // one Richardson update of x into out for every element, with the residual tile sums
+template <typename TC>
+dg_status rich_update_valu(const dg_mesh* m, const double* x, const double* g, const double* u,
+                           double* out, double tau, double ds, const int* stop, hipStream_t s) {
+  auto a = base_args<double, TC>(m);
+  a.x = x; a.u = u; a.w0 = g; a.out = out; a.mode = 2; a.tau = tau; a.ds = ds;
+  a.absdet = m->d_absdet; a.partial = m->d_rich_partial; a.stop = stop;
+  HIP_TRY(launch_conv_any(m, a, s));
+  return DG_OK;
+}
+
+// engine >= 0: the matrix-core kernel; -1: the FP64 VALU kernel; -2: the VALU kernel with
+// FP32 contractions (DG_MIX_F32)
 dg_status rich_update(const dg_mesh* m, int engine, const double* x, const double* g,
                       const double* u, double* out, double tau, double ds, const int* stop,
                       hipStream_t s, int* nparts) {
@@ -576,11 +596,9 @@ dg_status rich_update(const dg_mesh* m, int engine, const double* x, const doubl
     *nparts = m->h.ntiles16;
     HIP_TRY(launch_mconv_any(m, engine, a, s));
   } else {
-    auto a = base_args<double>(m);
-    a.x = x; a.u = u; a.w0 = g; a.out = out; a.mode = 2; a.tau = tau; a.ds = ds;
-    a.absdet = m->d_absdet; a.partial = m->d_rich_partial; a.stop = stop;
     *nparts = m->h.ntiles;
-    HIP_TRY(launch_conv_any<double>(m, a, s));
+    return engine == -2 ? rich_update_valu<float>(m, x, g, u, out, tau, ds, stop, s)
+                        : rich_update_valu<double>(m, x, g, u, out, tau, ds, stop, s);
   }
   return DG_OK;
 }
@@ -861,8 +879,7 @@ dg_status apply_common(const dg_mesh* m, dg_precision prec, const void* w, const
   if (!aligned16(w) || !aligned16(r) || (u && !aligned16(u)))
     return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
   if (r == w || r == u) return fail(DG_EINVAL, "r must not alias w or u");
-  if (prec != DG_FP64 && prec != DG_FP32 && prec != DG_MIX_F16x2 && prec != DG_MIX_BF16x3)
-    return fail(DG_EINVAL, "unknown precision");
+  if (!known_precision(prec)) return fail(DG_EINVAL, "unknown precision");
   dg_status st = ensure_device(m);
   if (st != DG_OK) return st;
   const hipStream_t s = (hipStream_t)stream;
@@ -871,6 +888,7 @@ dg_status apply_common(const dg_mesh* m, dg_precision prec, const void* w, const
   switch (prec) {
     case DG_FP64: return run_apply<double>(m, w, u, r, s, bc);
     case DG_FP32: return run_apply<float>(m, w, u, r, s, bc);
+    case DG_MIX_F32: return run_apply<double, float>(m, w, u, r, s, bc);
     default: return fail(DG_EUNSUPPORTED, "precision not available for dg_convection_apply");
   }
 }
@@ -919,8 +937,7 @@ dg_status rk_common(const dg_mesh* m, dg_precision prec, void* w, double dt, int
   if (!aligned16(w) || (u && !aligned16(u)) || (work && !aligned16(work)))
     return fail(DG_EINVAL, "state pointers must be 16-byte aligned");
   if (u == w) return fail(DG_EINVAL, "u must not alias w");
-  if (prec != DG_FP64 && prec != DG_FP32 && prec != DG_MIX_F16x2 && prec != DG_MIX_BF16x3)
-    return fail(DG_EINVAL, "unknown precision");
+  if (!known_precision(prec)) return fail(DG_EINVAL, "unknown precision");
   dg_status st = ensure_device(m);
   if (st != DG_OK) return st;
   const int engine = engine_of(m, prec, u != nullptr);
@@ -941,6 +958,7 @@ dg_status rk_common(const dg_mesh* m, dg_precision prec, void* w, double dt, int
   }
   const hipStream_t s = (hipStream_t)stream;
   if (engine >= 0) return run_rk_m(m, engine, w, dt, n, u, work, s, ex, bc);
+  if (prec == DG_MIX_F32) return run_rk<double, float>(m, w, dt, n, u, work, s, ex, bc);
   return prec == DG_FP64 ? run_rk<double>(m, w, dt, n, u, work, s, ex, bc)
                          : run_rk<float>(m, w, dt, n, u, work, s, ex, bc);
 }
@@ -976,11 +994,10 @@ dg_status dg_richardson(const dg_mesh* m, dg_precision prec, double* v, const do
       !std::isfinite(rtol) || max_it < 0)
     return fail(DG_EINVAL, "need finite tau, ds > 0, rtol >= 0, max_it >= 0");
   if (prec == DG_FP32) return fail(DG_EUNSUPPORTED, "the iteration runs on FP64 states");
-  if (prec != DG_FP64 && prec != DG_MIX_F16x2 && prec != DG_MIX_BF16x3)
-    return fail(DG_EINVAL, "unknown precision");
+  if (!known_precision(prec)) return fail(DG_EINVAL, "unknown precision");
   dg_status st = ensure_device(m);
   if (st != DG_OK) return st;
-  const int engine = engine_of(m, prec, u != nullptr);
+  const int engine = prec == DG_MIX_F32 ? -2 : engine_of(m, prec, u != nullptr);
   if (engine >= 0 && (st = ensure_frags(m, engine)) != DG_OK) return st;
   if (!work) {
     std::lock_guard<std::mutex> lock(const_cast<dg_mesh*>(m)->mu);

@@ -19,10 +19,13 @@
 //   EngF64        v_mfma_f64_16x16x4 (four per K = 16 chunk); the FP64 path.
 //   EngSplit<..>  v_mfma_f32_16x16x16 on FP16 or BF16 pieces: x = x0 + x1 (+ x2) split by
 //                 successive rounding, products x_a y_b with a + b < pieces (3 or 6 MFMAs),
-//                 FP32 accumulation inside one K chunk, FP64 accumulation across chunks.
-//                 FP16 operands are scaled per element and chunk by a power of two so the
-//                 largest magnitude sits in [1, 2).  The flux, the facet sums, the state and
-//                 the Runge-Kutta update stay FP64.
+//                 FP32 accumulation inside one K chunk.  Across K chunks the facet lifts are
+//                 folded into FP64 accumulators (mma_into), while the volume interpolation W
+//                 and the volume test contraction Rv keep accumulating in FP32 (mma_acc) and
+//                 reach FP64 only when the volume term is added to R.  FP16 operands are
+//                 scaled per element and chunk by a power of two so the largest magnitude
+//                 sits in [1, 2).  The flux, the facet sums, the state and the Runge-Kutta
+//                 update stay FP64.
 #pragma once
 #include <hip/hip_runtime.h>
 

@@ -547,6 +547,9 @@ dg_status dg_surrogate_create(const dg_mesh* m, int M, dg_surrogate** out) {
   if (M < 1) return fail(DG_EINVAL, "M must be >= 1");
   if ((m->h.dim + 2) * m->h.dim * m->h.np != kIn || m->h.dim * m->h.np != kOut)
     return fail(DG_EUNSUPPORTED, "the network is built for 2D P3 elements (80 inputs, 20 outputs)");
+  // the inputs gather every face neighbour's coefficients: a boundary facet has none
+  if (m->h.nbf > 0)
+    return fail(DG_EUNSUPPORTED, "the network needs a mesh without boundary facets");
   dg_status st = dgi::ensure_device(m);
   if (st != DG_OK) return st;
   dg_surrogate* s = new (std::nothrow) dg_surrogate();
@@ -692,16 +695,22 @@ dg_status dg_surrogate_train_step(dg_surrogate* s, const float* x, const float* 
 }
 
 dg_status dg_macro_step(const dg_mesh* m, dg_surrogate* s, double* w, double dt, double tol,
-                        int* accepted, double* rho_out, void* stream) {
+                        void* work, int* accepted, double* rho_out, void* stream) {
   if (!m || !s || !w || !accepted) return fail(DG_EINVAL, "null pointer");
-  if (!al16(w)) return fail(DG_EINVAL, "w must be 16-byte aligned");
+  if (!al16(w) || (work && !al16(work))) return fail(DG_EINVAL, "w and work must be 16-byte aligned");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(DG_EINVAL, "dt must be positive and finite");
   if (m->h.E != s->E) return fail(DG_EINVAL, "surrogate was created for another mesh");
   const hipStream_t hs = (hipStream_t)stream;
   const int64_t E = s->E;
   const int per = s->dim * s->np;
   const size_t n_state = (size_t)E * per;
-  double* wt = s->mwork;
+  if (work) {
+    const char* wb = (const char*)work;
+    const char* ww = (const char*)w;
+    if (wb < ww + n_state * 8 && ww < wb + 3 * n_state * 8)
+      return fail(DG_EINVAL, "work must not overlap w");
+  }
+  double* wt = work ? (double*)work : s->mwork;
   double* r0 = wt + n_state;
   double* r1 = r0 + n_state;
   dg_status st = ensure_cap(s, E);

@@ -41,7 +41,7 @@ def wave(x, A=0.3):
 CASES = [(2, 2, 13, (False, True), 0.2), (2, 4, 7, (False, True), 0.2),
          (3, 2, 3, (False, True, False), 0.1), (3, 3, 3, (False, True, False), 0.1)]
 VARIANTS = [("fp64", "valu", 1e-12), ("fp64", "mfma", 1e-12), ("fp32", None, 1e-4),
-            ("bf16x3", None, 1e-5), ("f16x2", None, 1e-4)]
+            ("bf16x3", None, 1e-5), ("f16x2", None, 1e-4), ("mixf32", None, 1e-5)]
 
 
 @pytest.mark.parametrize("dim,k,N,per,jit", CASES)

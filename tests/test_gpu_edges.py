@@ -34,7 +34,8 @@ def test_one_cell_meshes(dg, dim, k):
     w = initial_state(sp, seed=3, sd=0.1)
     u = initial_state(sp, field="fourier", seed=4)
     for kern, prec, tol in [("valu", "fp64", 1e-12), ("mfma", "fp64", 1e-12),
-                            (None, "fp32", 1e-4), (None, "bf16x3", 1e-5)]:
+                            (None, "fp32", 1e-4), (None, "bf16x3", 1e-5),
+                            (None, "mixf32", 1e-5)]:
         if kern:
             os.environ["DGCONV_FP64_KERNEL"] = kern
         else:
@@ -60,7 +61,7 @@ def test_zero_substeps_and_zero_state(dg):
     m.rk_substeps(w, 1e-3, 0)
     assert torch.equal(w, w0)
     z = torch.zeros_like(w)
-    for prec in ("fp64", "bf16x3", "f16x2"):
+    for prec in ("fp64", "bf16x3", "f16x2", "mixf32"):
         r = m.apply(z, precision=prec)
         assert not r.any(), prec
     zf = torch.zeros(w.shape, dtype=torch.float32, device="cuda")

@@ -38,7 +38,7 @@ def dev(a, dtype=torch.float64):
 CASES = [(2, 2, 13, 0.2), (2, 4, 7, 0.2), (3, 2, 3, 0.15), (3, 3, 3, 0.15)]
 # precision, FP64 kernel, relative L2 bar of the final state
 VARIANTS = [("fp64", "valu", 1e-12), ("fp64", "mfma", 1e-12), ("fp32", None, 1e-4),
-            ("bf16x3", None, 1e-6), ("f16x2", None, 1e-5)]
+            ("bf16x3", None, 1e-6), ("f16x2", None, 1e-5), ("mixf32", None, 1e-5)]
 
 
 @pytest.mark.parametrize("dim,k,N,jit", CASES)

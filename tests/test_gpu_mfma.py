@@ -126,3 +126,38 @@ def test_mixed_c5_substeps(dg, prec):
     amp = 1.0 / (2 * np.pi / N)
     assert e_apply <= 64 * BOUND[prec] * amp
     assert e_state <= 1e-6
+
+
+@pytest.mark.parametrize("dim,k,N,jit", CASES)
+def test_mixf32_apply_all_degrees(dg, dim, k, N, jit):
+    """FP64 state, flux, facet sums and update around FP32 contractions (the vector-unit
+    kernel), self and frozen mode, every compiled degree, against the FP64 oracle.  Bar: the
+    FP32 contraction model of test_gpu_parity.full_bars (16 u / (2 pi h), u = 2^-24)."""
+    say("case mixf32 apply dim=%d k=%d" % (dim, k))
+    sp = oracle_space(dim, N, k, jit, seed=k)
+    m = lib_mesh(dg, sp, dim, N, k, jit, {})
+    w = initial_state(sp, seed=1, sd=0.05)
+    u = initial_state(sp, field="fourier", seed=2)
+    bar = 16 * 2.0 ** -24 * max(1.0, N / (2 * np.pi))
+    for uu in (None, u):
+        got = m.apply(dev(w), None if uu is None else dev(uu), precision="mixf32").cpu().numpy()
+        e = rel_l2(sp, got, sp.apply(w, uu))
+        say("   %s rel_l2 %.3e (bar %.1e)" % ("frozen" if uu is not None else "self", e, bar))
+        assert e <= bar
+
+
+def test_mixf32_c5_substeps(dg):
+    dim, N, k = C5
+    say("case mixf32 c5 apply + 4 substeps")
+    sp = oracle_space(dim, N, k)
+    m = dg.Mesh.box(dim, N, k)
+    w = initial_state(sp, field="fourier", seed=3)
+    r = m.apply(dev(w), precision="mixf32").cpu().numpy()
+    e_apply = rel_l2(sp, r, sp.apply(w))
+    dt = cfl_dt(1.0 / N, k, sp.max_speed(w))
+    wd = dev(w)
+    m.rk_substeps(wd, dt, 4, precision="mixf32")
+    e_state = rel_l2(sp, wd.cpu().numpy(), sp.ssprk3(w, dt, 4))
+    say("   apply rel_l2 %.3e  state after 4 substeps rel_l2 %.3e" % (e_apply, e_state))
+    assert e_apply <= 16 * 2.0 ** -24 * N / (2 * np.pi)
+    assert e_state <= 1e-6

@@ -93,35 +93,85 @@ def test_c5_apply_and_substeps(dg):
     check(sp, wd.cpu().numpy(), sp.ssprk3(w, dt, 1, u))
 
 
-@pytest.mark.parametrize("cfg,field", [(C2, "tg"), (C3, "tg"), (C4, "fourier")])
-def test_full_size_sampled(dg, cfg, field):
-    """Full-size meshes: one apply and one fused SSP-RK3 substep (the benchmark launch
-    configuration), checked on sampled elements the oracle evaluates one by one."""
+_FULL = {}
+
+
+def full_case(cfg, field):
+    """Full-size mesh, its initial state, sampled elements and the oracle's values there (one
+    configuration is kept at a time: the 3D 64^3 x 6 mesh alone holds 1.5M elements)."""
+    key = (cfg, field)
+    if key not in _FULL:
+        _FULL.clear()
+        dim, N, k = cfg
+        sp = oracle_space(dim, N, k)
+        w = initial_state(sp, field=field, seed=0)
+        rng = np.random.default_rng(7)
+        sample = np.unique(np.concatenate([rng.choice(sp.mesh.E, 300, replace=False),
+                                           [0, sp.mesh.E - 1]]))
+        ref_apply = sp.apply(w, elems=sample)
+        dt = cfl_dt(1.0 / N, k, 3.0)  # any positive step: a bound on max|w| for these fields
+        S, ref_rk = oracle_rk_on_sample(sp, w, dt, sample[:60])
+        _FULL[key] = (sp, w, sample, ref_apply, dt, S, ref_rk)
+    return _FULL[key]
+
+
+# (configuration, field, precision, apply bar, substep bar); the FP64 bars are the parity bar,
+# the others are derived in test_full_size_sampled's docstring
+FULL_CASES = [
+    (C2, "tg", "fp64"), (C2, "tg", "fp32"),
+    (C3, "tg", "fp64"), (C3, "tg", "f16x2"), (C3, "tg", "bf16x3"),
+    (C4, "fourier", "fp64"), (C4, "fourier", "fp32"), (C4, "fourier", "mixf32"),
+    (C4, "fourier", "f16x2"), (C4, "fourier", "bf16x3"),
+]
+
+
+def full_bars(prec, cfg):
+    """(apply bar, substep bar) for relative L2 over the sampled elements.
+
+    FP64: the parity bar.  Lower precisions: a contraction rounded at unit roundoff u (FP32
+    operands and sums: 2^-24; the split pieces: 2^-22 for two FP16 pieces, 2^-24 for three
+    BF16 pieces) perturbs the volume and facet terms by about u times their size; the operator
+    is their difference, smaller by the cancellation factor ~ 2 pi h (the fields' wavelength
+    is the box), so r carries a relative error of about u / (2 pi h).  The bar is 16 times
+    that.  After one substep the error is dt r's, relative to the state: smaller by dt |r| / |w|
+    ~ 0.1 / k^2; an FP32 state adds its own rounding (2^-24 relative), so its substep bar is
+    16 (2^-24 + 0.1 u / (2 pi h k^2))."""
     dim, N, k = cfg
-    say("case full-size sampled dim=%d N=%d k=%d" % (dim, N, k))
-    sp = oracle_space(dim, N, k)
+    if prec == "fp64":
+        return TOL, TOL
+    u = {"fp32": 2.0 ** -24, "mixf32": 2.0 ** -24, "f16x2": 2.0 ** -22, "bf16x3": 2.0 ** -24}[prec]
+    amp = N / (2 * np.pi)
+    state = 2.0 ** -24 if prec == "fp32" else 0.0
+    return 16 * u * amp, 16 * (state + 0.1 * u * amp / k ** 2)
+
+
+@pytest.mark.parametrize("cfg,field,prec", FULL_CASES)
+def test_full_size_sampled(dg, cfg, field, prec):
+    """Full-size meshes: one apply and one fused SSP-RK3 substep (the benchmark launch
+    configuration), checked on sampled elements the oracle evaluates one by one, for the FP64
+    path and for the FP32, FP32-contraction and split-product variants the configurations name
+    (bars: full_bars)."""
+    dim, N, k = cfg
+    say("case full-size sampled dim=%d N=%d k=%d %s" % (dim, N, k, prec))
+    sp, w, sample, ref, dt, S, ref1 = full_case(cfg, field)
+    bar_apply, bar_rk = full_bars(prec, cfg)
+    ty = torch.float32 if prec == "fp32" else torch.float64
     m = dg.Mesh.box(dim, N, k)
-    w = initial_state(sp, field=field, seed=0)
-    rng = np.random.default_rng(7)
-    sample = np.unique(np.concatenate([rng.choice(sp.mesh.E, 300, replace=False),
-                                       [0, sp.mesh.E - 1]]))
-    wd = dev(w)
-    r = m.apply(wd).cpu().numpy()
-    ref = sp.apply(w, elems=sample)
+    wd = dev(w, ty)
+    r = m.apply(wd, precision=prec).double().cpu().numpy()
     J = sp.mesh.absdetJ[sample]
     e = rel_l2_rows(J, r[sample], ref)
-    say("   apply sampled rel_l2 %.3e" % e)
-    assert e <= TOL
-    # properties that hold at any size: conservation of the discrete momentum
-    mom = m.reduce("momentum", torch.tensor(r, device="cuda", dtype=torch.float64)).cpu().numpy()
-    assert np.abs(mom[:dim]).max() <= 1e-12 * np.abs(r).max()
-    dt = cfl_dt(1.0 / N, k, 3.0)  # any positive step: a bound on max|w| for these fields
-    m.rk_substeps(wd, dt, 1)
-    got = wd.cpu().numpy()
-    S, ref1 = oracle_rk_on_sample(sp, w, dt, sample[:60])
+    say("   apply sampled rel_l2 %.3e (bar %.1e)" % (e, bar_apply))
+    assert e <= bar_apply
+    if prec == "fp64":
+        # properties that hold at any size: conservation of the discrete momentum
+        mom = m.reduce("momentum", torch.tensor(r, device="cuda", dtype=torch.float64)).cpu().numpy()
+        assert np.abs(mom[:dim]).max() <= 1e-12 * np.abs(r).max()
+    m.rk_substeps(wd, dt, 1, precision=prec)
+    got = wd.double().cpu().numpy()
     e = rel_l2_rows(sp.mesh.absdetJ[S], got[S], ref1)
-    say("   substep sampled rel_l2 %.3e" % e)
-    assert e <= TOL
+    say("   substep sampled rel_l2 %.3e (bar %.1e)" % (e, bar_rk))
+    assert e <= bar_rk
 
 
 def test_reductions(dg):

@@ -58,7 +58,8 @@ def test_richardson_vs_oracle(dg, dim, k, N, jit):
     r = np.array(hist) / hist[0]
     # the stopping decision is not borderline, so both sides must take it at the same update
     assert r[-1] < RTOL * (1 - 1e-6) and r[-2] > RTOL * (1 + 1e-6)
-    for prec, kern in [("fp64", "valu"), ("fp64", "mfma"), ("bf16x3", None), ("f16x2", None)]:
+    for prec, kern in [("fp64", "valu"), ("fp64", "mfma"), ("bf16x3", None), ("f16x2", None),
+                       ("mixf32", None)]:
         if kern:
             os.environ["DGCONV_FP64_KERNEL"] = kern
         else:

@@ -28,6 +28,11 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def rel_l2(a, b):
+    """Relative L2 difference of two states on a box mesh (all elements have one measure)."""
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
 def test_features_and_targets(env):
     dg, S, mesh, sur = env
     say("case surrogate features")
@@ -187,3 +192,71 @@ def test_warm_start_matches_its_definition(env):
         sur.warm_start(g, None, 0.0)
     with pytest.raises(dg.DGError):
         sur.warm_start(g, None, tau, out=g)
+
+
+def test_macro_step_matches_the_oracle(env):
+    """dg_macro_step against oracle/macro.py (candidate, trapezoid defect, decision).
+
+    Given the network output the library produced (BF16 kernels), everything after it is FP64
+    on both sides: the increment w~ - w must agree to 1e-12 relative L2 (the operator's own
+    parity bar).  The defect rho = ||w~ - w - tau/2 (r(w) + r(w~))|| / ||w~ - w|| is a ratio of
+    a small residual: its numerator nu carries the operator's parity error on both
+    applications (<= 1e-13 relative, times tau/2 (||r(w)|| + ||r(w~)||)) and the rounding of
+    the FP64 states it is recovered from (eps ||w||), so the bar is 4 (1e-13 tau/2 (||r0|| +
+    ||r1||) + 2 eps ||w||) / nu + 1e-13 relative.  The decision is checked at tolerances a
+    factor 2 away from rho, where both sides must agree, and the fallback against the
+    oracle's 8 substeps (1e-12).  Against the FP64 network oracle the defect differs by the
+    BF16 network error (the 3e-2 bar of this file)."""
+    from oracle import macro
+    from oracle.dg import Space
+    from oracle.mesh import box_mesh
+    dg, S, mesh, sur = env
+    say("case macro-step vs oracle")
+    p = (mlp.init_params(21) * 0.5).astype(np.float32)
+    sur.load(p)
+    p64 = p.astype(np.float64)
+    sp = Space(box_mesh(2, 16), 3)
+    w_h = S.initial_state(mesh, 22)
+    w = torch.tensor(w_h, device="cuda")
+    h = mesh.info["h_min"]
+    n_s = (3 * 3 + 1) // 2
+    s_o = macro.scale(sp, w_h, n_s)
+    scale = mesh.reduce("maxvel", w)
+    assert abs(scale[0].item() - s_o) <= 1e-13 * s_o
+    dt = 0.1 * h / (9 * s_o)
+    tau = 8 * dt
+    y = sur.forward(sur.features(w, scale)).double().cpu().numpy()
+    _, acc_o, rho_o, wt_o = macro.macro_step(sp, p64, w_h, dt, 8, np.inf, h, n_s, y=y)
+    ws = w.clone()
+    acc, rho = sur.macro_step(ws, dt, np.inf)
+    assert acc and acc_o
+    inc_o = wt_o - w_h
+    e_inc = rel_l2(ws.cpu().numpy() - w_h, inc_o)
+    r0, r1 = sp.apply(w_h), sp.apply(wt_o)
+    nu = sp.l2_norm(inc_o - 0.5 * tau * (r0 + r1))
+    bar = 4 * (1e-13 * 0.5 * tau * (sp.l2_norm(r0) + sp.l2_norm(r1)) +
+               2 * np.finfo(float).eps * sp.l2_norm(w_h)) / nu + 1e-13
+    e_rho = abs(rho - rho_o) / rho_o
+    say("   increment rel %.3e  rho %.6e vs %.6e (rel %.3e, bar %.1e)" % (e_inc, rho, rho_o, e_rho, bar))
+    assert e_inc <= 1e-12
+    assert e_rho <= bar
+    # the decision at tolerances a factor 2 away from rho, and the fallback
+    wa = w.clone()
+    acc, _ = sur.macro_step(wa, dt, 2 * rho_o)
+    out_o, acc_o, _, _ = macro.macro_step(sp, p64, w_h, dt, 8, 2 * rho_o, h, n_s, y=y)
+    assert acc and acc_o and torch.equal(wa, ws)
+    wr = w.clone()
+    work = torch.empty((3,) + tuple(w.shape), dtype=torch.float64, device="cuda")
+    acc, _ = sur.macro_step(wr, dt, 0.5 * rho_o, work=work)
+    out_o, acc_o, _, _ = macro.macro_step(sp, p64, w_h, dt, 8, 0.5 * rho_o, h, n_s, y=y)
+    assert not acc and not acc_o
+    e_fb = rel_l2(wr.cpu().numpy(), out_o)
+    say("   fallback vs oracle 8 substeps rel %.3e" % e_fb)
+    assert e_fb <= 1e-12
+    # the FP64 network oracle: the defect agrees to the BF16 network's accuracy
+    _, _, rho_64, wt_64 = macro.macro_step(sp, p64, w_h, dt, 8, np.inf, h, n_s)
+    e_net = abs(rho - rho_64) / rho_64
+    say("   rho vs FP64-network oracle %.6e (rel %.3e)" % (rho_64, e_net))
+    assert e_net < 3e-2
+    with pytest.raises(dg.DGError):  # work overlapping w
+        sur.macro_step(work[1], dt, 1.0, work=work)

@@ -62,7 +62,7 @@ def test_shuffled_frames_vs_oracle(dg, dim, k, N, per):
     E = om.E
     for lane in ("1", "0"):
         os.environ["DGCONV_LANE_TABLES"] = lane
-        for prec in ("fp64", "fp32"):
+        for prec in ("fp64", "fp32", "mixf32"):
             say("   lane tables %s, %s" % (lane, prec))
             m = dg.Mesh.from_arrays(dim, k, om.X.reshape(-1, dim),
                                     np.arange(E * (dim + 1)).reshape(E, dim + 1), om.period)

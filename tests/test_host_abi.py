@@ -224,6 +224,24 @@ def test_boundary_mesh_needs_the_bc_entry_points():
                            None) == -4
 
 
+def test_surrogate_rejects_meshes_with_boundary_facets():
+    """The network's inputs gather the neighbour across every facet, so a mesh with boundary
+    facets is refused at creation, before any device work (and other element types too)."""
+    from oracle.mesh import box_mesh
+    om = box_mesh(2, 4, periodic=(False, True))
+    E = om.E
+    m = dg.Mesh.from_arrays(2, 3, om.X.reshape(-1, 2), np.arange(E * 3).reshape(E, 3),
+                            np.array([0.0, 1.0]))
+    assert m.info["n_bfacet"] > 0
+    h = ctypes.c_void_p()
+    assert dg.lib().dg_surrogate_create(m._h, 8, ctypes.byref(h)) == -4
+    assert b"boundary" in dg.lib().dg_last_error()
+    assert not h.value
+    m2 = dg.Mesh.box(2, 4, 2)
+    assert dg.lib().dg_surrogate_create(m2._h, 8, ctypes.byref(h)) == -4
+    assert not h.value
+
+
 @pytest.mark.parametrize("dim,k", [(2, 1), (2, 2), (2, 4), (2, 6), (3, 1), (3, 2), (3, 3), (3, 4)])
 def test_hdiv_reference_basis_matches_the_oracle(dim, k):
     """The library's reference dual basis (long double Gauss-Jordan of its own moment matrix)

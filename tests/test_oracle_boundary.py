@@ -51,8 +51,6 @@ def test_energy_identity_with_zero_outer_data(dim, N, per, jit, k):
     """Frozen constant u (divergence-free, continuous): <w, M r> = -1/2 sum_F int |u.n| |[w]|^2
     with [w] = w^- - 0 on boundary facets: interior facets dissipate as before, outflow facets
     carry 1/2 (u.n)|w|^2 out, and zero inflow data takes 1/2 |u.n| |w|^2 away."""
-    if dim == 3 and k == 3:
-        pytest.skip("size")
     m = box_mesh(dim, N, jitter=jit, seed=4, periodic=per)
     sp = Space(m, k)
     v = [0.8, -0.45, 0.3][:dim]

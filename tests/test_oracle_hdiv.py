@@ -35,14 +35,20 @@ MESHES_2D = ["bounded", "jittered", "shuffled"]
 MESHES_3D = ["bounded3", "jittered3", "shuffled3"]
 
 
-@pytest.mark.parametrize("name,k", [(n, k) for n in MESHES_2D for k in (1, 2, 3, 4)] +
+@pytest.mark.parametrize("name,k", [(n, k) for n in MESHES_2D for k in (1, 2, 3, 4, 5, 6)] +
                          [(n, k) for n in MESHES_3D for k in (1, 2, 3)] + [("shuffled3", 4)])
 def test_dof_duality(name, k):
-    """The dof functionals, evaluated directly on the DG field I u, give back u."""
+    """The dof functionals, evaluated directly on the DG field I u, give back u.
+
+    The reference dual basis is the inverse of the reference moment matrix G, whose condition
+    number grows with k (2D: 5e3 at k = 4, 6e4 at k = 5, 7e5 at k = 6: the Nedelec and facet
+    moments of a monomial-based spanning set).  Inverting it in FP64 costs about eps cond(G)
+    relative accuracy, so the bar is 1e-11 or 32 eps cond(G) max|u|, whichever is larger."""
     m = MESHES[name]()
     H = HdivSpace(m, k)
     u = np.random.default_rng(k).normal(size=H.N)
-    assert np.abs(H.dofs(H.to_dg(u)) - u).max() < 1e-11
+    bar = max(1e-11, 32 * np.finfo(float).eps * np.linalg.cond(H.C) * np.abs(u).max())
+    assert np.abs(H.dofs(H.to_dg(u)) - u).max() < bar
 
 
 @pytest.mark.parametrize("name", sorted(MESHES))

@@ -42,6 +42,35 @@ def test_adam_first_step_closed_form():
     assert np.allclose(p1, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
 
 
+def test_adam_later_steps_closed_form():
+    # a constant gradient g: m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so with the bias
+    # correction every step moves by lr g / (|g| + eps); a wrong correction exponent at t >= 2
+    # (or none) changes steps 2 and 3
+    g = np.array([0.3, -2.0, 1e-3, 7.5])
+    opt = mlp.Adam(4)
+    p = np.zeros(4)
+    for t in range(1, 4):
+        p = opt.step(p, g, 0.01)
+        assert np.allclose(p, -0.01 * t * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0), t
+    # a gradient that flips sign at t = 2: m_2 = (b1 (1 - b1) - (1 - b1)) g, v_2 = (1 - b2^2) g^2
+    opt = mlp.Adam(4)
+    p1 = opt.step(np.zeros(4), g, 0.01)
+    p2 = opt.step(p1, -g, 0.01)
+    mh = (0.9 * 0.1 - 0.1) / (1 - 0.9 ** 2)
+    assert np.allclose(p2 - p1, -0.01 * mh * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=0)
+
+
+def test_adam_is_invariant_to_gradient_scale():
+    rng = np.random.default_rng(4)
+    gs = [rng.normal(size=50) for _ in range(4)]
+    a, b = mlp.Adam(50, eps=0.0), mlp.Adam(50, eps=0.0)
+    pa = pb = np.zeros(50)
+    for g in gs:
+        pa = a.step(pa, g, 1e-2)
+        pb = b.step(pb, 1000.0 * g, 1e-2)
+    assert np.allclose(pa, pb, rtol=1e-12, atol=1e-15)
+
+
 def test_loss_decreases_on_a_linear_target():
     rng = np.random.default_rng(3)
     p = mlp.init_params(2)
