@@ -248,6 +248,18 @@ enum { DG_RED_MAXVEL = 0, DG_RED_ENERGY = 1, DG_RED_MOMENTUM = 2, DG_RED_L2DIFF 
 dg_status dg_reduce(const dg_mesh* mesh, int what, const double* a, const double* b,
                     double* out_dev, void* stream);
 
+/* dg_reduce for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same reductions, the same kernels and
+ * the same results, with the per-block partial results in a static device array of the
+ * library (768 KiB per device, held until the process ends) instead of the mesh's buffer.
+ * No memory is allocated: the mesh's device tables must already be resident on the current
+ * device (any earlier compute call there uploads them; DG_EINVAL otherwise).  Meshes of at
+ * most 8 388 608 elements (DG_EINVAL above).  Every call on one device shares the array:
+ * calls that overlap in time on one device (other streams, other threads, other meshes)
+ * race and must be serialised by the caller.  Other arguments and errors as dg_reduce. */
+dg_status dg_reduce_noalloc(const dg_mesh* mesh, int what, const double* a, const double* b,
+                            double* out_dev, void* stream);
+
 /* ---- Learned macro-step (2D, P3 elements): a per-element network replaces M substeps.
  * Network 80 -> 256 -> 256 -> 256 -> 20 with erf-GELU; BF16 matrix-core kernels with FP32
  * accumulation, FP32 master weights, Adam.  Flat FP32 parameters: W1 [256][80], b1 [256],

@@ -66,6 +66,7 @@ def lib():
         "dg_rk_substeps_bc": [P, I, P, D, I, P, P, P, P, P],
         "dg_richardson": [P, I, P, P, P, D, D, D, I, P, P, P, P],
         "dg_reduce": [P, I, P, P, P, P],
+        "dg_reduce_noalloc": [P, I, P, P, P, P],
         "dg_eval_basis": [I, I, I64, P, P, P],
         "dg_surrogate_n_params": [P],
         "dg_surrogate_create": [P, I, P],
@@ -294,6 +295,14 @@ class Mesh:
         _check(lib().dg_reduce(self._h, RED[what], _dev(a, torch.float64),
                                None if b is None else _dev(b, torch.float64),
                                _dev(out, torch.float64), _stream(stream)))
+        return out
+
+    def reduce_noalloc(self, what, a, b, out, stream=None):
+        """dg_reduce_noalloc: out (a caller tensor, >= dim doubles) is required."""
+        import torch
+        _check(lib().dg_reduce_noalloc(self._h, RED[what], _dev(a, torch.float64),
+                                       None if b is None else _dev(b, torch.float64),
+                                       _dev(out, torch.float64), _stream(stream)))
         return out
 
 

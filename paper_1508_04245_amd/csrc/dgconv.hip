@@ -142,10 +142,10 @@ final_reduce_kernel(int nblocks, int is_max, int nout, int sqrt_out,
 
 // ------------------------------------------------------------------ dispatch
 template <int D, int K>
-hipError_t launch_maxvel(const dg_mesh* m, const double* a, hipStream_t s) {
+hipError_t launch_maxvel(const dg_mesh* m, const double* a, double* partial, hipStream_t s) {
   const int nb = (int)((m->h.E + kRedBlock - 1) / kRedBlock);
   hipLaunchKernelGGL((maxvel_kernel<D, K>), dim3(nb), dim3(kRedBlock), 0, s, m->h.E, a,
-                     m->d_tab, m->d_partial);
+                     m->d_tab, partial);
   return hipGetLastError();
 }
 
@@ -720,6 +720,71 @@ void free_mesh(dg_mesh* m) {
   delete m;
 }
 
+// Static scratch of dg_reduce_noalloc: the per-block partial results (3 doubles per block of
+// kRedBlock elements), one copy per device, held until the process ends.  In host code the
+// array's name is no device address: kernels get the address hipGetSymbolAddress returns for
+// the current device (kept per device below).  Every call on one device shares it.
+constexpr int kScratchBlocks = 32768;  // meshes of up to 8 388 608 elements (768 KiB)
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchBlocks * 3];
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of this device's scratch, looked up once per device (the device is
+// current); no memory is allocated
+dg_status scratch_of_device(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(DG_EUNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(DG_EDEVICE, "no device address for the reduction scratch");
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DG_OK;
+}
+
+dg_status check_reduce(const dg_mesh* m, int what, const double* a, const double* b,
+                       const double* out_dev) {
+  if (!m || !a || !out_dev) return fail(DG_EINVAL, "null pointer");
+  if (what < DG_RED_MAXVEL || what > DG_RED_NONFINITE) return fail(DG_EINVAL, "unknown reduction");
+  if (what == DG_RED_L2DIFF && !b) return fail(DG_EINVAL, "L2DIFF needs b");
+  return DG_OK;
+}
+
+// the reductions of dg_reduce with the per-block partial results in `partial` (at least
+// 3 n_partial doubles; every block writes its own entries before the final pass reads them,
+// so nothing needs clearing)
+dg_status run_reduce(const dg_mesh* m, int what, const double* a, const double* b,
+                     double* out_dev, double* partial, hipStream_t s) {
+  const int nb = m->n_partial, d = m->h.dim;
+  if (what == DG_RED_MAXVEL) {
+    hipError_t e = hipErrorInvalidValue;
+    const int k = m->h.k;
+#define DG_CASE(D_, K_) \
+  if (d == D_ && k == K_) e = launch_maxvel<D_, K_>(m, a, partial, s);
+    DG_CASE(2, 0) DG_CASE(2, 1) DG_CASE(2, 2) DG_CASE(2, 3) DG_CASE(2, 4) DG_CASE(2, 5)
+    DG_CASE(2, 6) DG_CASE(3, 0) DG_CASE(3, 1) DG_CASE(3, 2) DG_CASE(3, 3) DG_CASE(3, 4)
+#undef DG_CASE
+    HIP_TRY(e);
+    hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(kRedBlock), 0, s, nb, 1, 1, 0,
+                       partial, out_dev);
+    HIP_TRY(hipGetLastError());
+    return DG_OK;
+  }
+  const double phi0_vol = d == 2 ? std::sqrt(2.0) * 0.5 : std::sqrt(6.0) / 6.0;
+  hipLaunchKernelGGL(elem_reduce_kernel, dim3(nb), dim3(kRedBlock), 0, s, what, d, m->h.np,
+                     m->h.E, a, b, m->d_absdet, phi0_vol, partial);
+  HIP_TRY(hipGetLastError());
+  const int nout = what == DG_RED_MOMENTUM ? d : (what == DG_RED_L2DIFF ? 2 : 1);
+  hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(kRedBlock), 0, s, nb, 0, nout,
+                     what == DG_RED_L2DIFF ? 1 : 0, partial, out_dev);
+  HIP_TRY(hipGetLastError());
+  return DG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1031,37 +1096,30 @@ dg_status dg_rk_substeps_extrap(const dg_mesh* m, dg_precision prec, void* w, do
 
 dg_status dg_reduce(const dg_mesh* m, int what, const double* a, const double* b,
                     double* out_dev, void* stream) {
-  if (!m || !a || !out_dev) return fail(DG_EINVAL, "null pointer");
-  if (what == DG_RED_L2DIFF && !b) return fail(DG_EINVAL, "L2DIFF needs b");
-  if (what < DG_RED_MAXVEL || what > DG_RED_NONFINITE) return fail(DG_EINVAL, "unknown reduction");
-  dg_status st = ensure_device(m);
+  dg_status st = check_reduce(m, what, a, b, out_dev);
   if (st != DG_OK) return st;
-  const hipStream_t s = (hipStream_t)stream;
-  const int nb = m->n_partial, d = m->h.dim;
-  if (what == DG_RED_MAXVEL) {
-    hipError_t e = hipErrorInvalidValue;
-    const int k = m->h.k;
-#define DG_CASE(D_, K_) \
-  if (d == D_ && k == K_) e = launch_maxvel<D_, K_>(m, a, s);
-    DG_CASE(2, 0) DG_CASE(2, 1) DG_CASE(2, 2) DG_CASE(2, 3) DG_CASE(2, 4) DG_CASE(2, 5)
-    DG_CASE(2, 6) DG_CASE(3, 0) DG_CASE(3, 1) DG_CASE(3, 2) DG_CASE(3, 3) DG_CASE(3, 4)
-#undef DG_CASE
-    HIP_TRY(e);
-    hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(kRedBlock), 0, s, nb, 1, 1, 0,
-                       m->d_partial, out_dev);
-    HIP_TRY(hipGetLastError());
-    return DG_OK;
-  }
-  if (what < DG_RED_ENERGY || what > DG_RED_NONFINITE) return fail(DG_EINVAL, "unknown reduction");
-  const double phi0_vol = d == 2 ? std::sqrt(2.0) * 0.5 : std::sqrt(6.0) / 6.0;
-  hipLaunchKernelGGL(elem_reduce_kernel, dim3(nb), dim3(kRedBlock), 0, s, what, d, m->h.np,
-                     m->h.E, a, b, m->d_absdet, phi0_vol, m->d_partial);
-  HIP_TRY(hipGetLastError());
-  const int nout = what == DG_RED_MOMENTUM ? d : (what == DG_RED_L2DIFF ? 2 : 1);
-  hipLaunchKernelGGL(final_reduce_kernel, dim3(1), dim3(kRedBlock), 0, s, nb, 0, nout,
-                     what == DG_RED_L2DIFF ? 1 : 0, m->d_partial, out_dev);
-  HIP_TRY(hipGetLastError());
-  return DG_OK;
+  if ((st = ensure_device(m)) != DG_OK) return st;
+  return run_reduce(m, what, a, b, out_dev, m->d_partial, (hipStream_t)stream);
+}
+
+dg_status dg_reduce_noalloc(const dg_mesh* m, int what, const double* a, const double* b,
+                            double* out_dev, void* stream) {
+  dg_status st = check_reduce(m, what, a, b, out_dev);
+  if (st != DG_OK) return st;
+  if (m->n_partial > kScratchBlocks)
+    return fail(DG_EINVAL, "mesh too large for dg_reduce_noalloc (at most " +
+                               std::to_string((long long)kScratchBlocks * kRedBlock) +
+                               " elements)");
+  // the mesh tables must be resident already: uploading them would allocate
+  if (!m->on_device)
+    return fail(DG_EINVAL, "the mesh's device tables are not resident yet (any other compute "
+                           "call on this device uploads them)");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != m->device) return fail(DG_EINVAL, "mesh was uploaded to another device");
+  double* partial = nullptr;
+  if ((st = scratch_of_device(dev, &partial)) != DG_OK) return st;
+  return run_reduce(m, what, a, b, out_dev, partial, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -273,3 +273,20 @@ def test_hdiv_size_matches_the_oracle():
     with pytest.raises(dg.DGError) as e:
         m0.hdiv_size()
     assert e.value.status == -1
+
+
+def test_reduce_noalloc_errors_before_device_work():
+    """dg_reduce_noalloc allocates nothing: a mesh above the static array's size and a mesh
+    whose tables are not resident yet are refused before any device call."""
+    L = dg.lib()
+    a, out = 4096, 8192  # never dereferenced: the checks fail first
+    big = dg.Mesh.box(2, 2049, 0)  # 8 396 802 triangles, above 8 388 608
+    assert L.dg_reduce_noalloc(big._h, 1, a, None, out, None) == -1
+    assert b"too large" in L.dg_last_error()
+    del big
+    m = dg.Mesh.box(2, 4, 2)
+    assert L.dg_reduce_noalloc(m._h, 1, a, None, out, None) == -1
+    assert b"resident" in L.dg_last_error()
+    assert L.dg_reduce_noalloc(m._h, 3, a, None, out, None) == -1  # L2DIFF without b
+    assert L.dg_reduce_noalloc(m._h, 9, a, None, out, None) == -1  # unknown reduction
+    assert L.dg_reduce_noalloc(m._h, 1, None, None, out, None) == -1
