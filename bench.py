@@ -9,9 +9,10 @@ operator-plus-stage launches).  Inputs are resident in device memory when timing
 The timed substeps run as one HIP graph (captured after the warm-up through torch's graph
 capture on the stream the library launches on), so the launches of the 3 K kernels are
 submitted at once; `--no-graph` times the eager launches instead.  Beside the headline the line
-carries the mixed variants on the same workload (the same K substeps from the same state:
-time per substep, final-state relative L2 error against FP64, the cheapest within 1e-6), the
-FP64 rate of the 3D 64^3 x 6 P2 workload, and the FP64 oracle on the host (all cores and one).
+carries the mixed variants on the same workload (the workload's own run length, 1000 substeps
+for the 2D 256^2 x 2 P4 one, from the same state in FP64 and in each variant: time per substep,
+final-state relative L2 error against FP64, the cheapest within 1e-6), the FP64 rate of the 3D
+64^3 x 6 P2 workload, and the FP64 oracle on the host (all cores and one).
 
 Prints one JSON line.  `--gpus N` with N > 1 is not supported (this benchmark runs on one GPU).
 """
@@ -373,11 +374,15 @@ def timed_substeps(m, w, dt, steps, work, prec, graph=True):
     return ev0.elapsed_time(ev1) / 1e3, wall
 
 
-def mixed_variants(m, w_start, w_ref, dt, steps, t64, ty64, graph=True, tol=1e-6):
-    """The same substeps from the same state in every lower-precision variant: time per
-    substep, final-state relative L2 error against the FP64 result w_ref, speedup over FP64,
-    and the cheapest variant within tol."""
+def mixed_variants(m, w_start, dt, steps, graph=True, tol=1e-6):
+    """`steps` substeps (the workload's own run length) from the same state in FP64 and in
+    every lower-precision variant: time per substep, final-state relative L2 error against
+    the FP64 result, speedup over FP64, and the cheapest variant within tol."""
     import torch
+    w_ref = w_start.to(torch.float64).clone()
+    work64 = torch.empty((2,) + tuple(w_ref.shape), dtype=torch.float64, device=w_ref.device)
+    t64, _ = timed_substeps(m, w_ref, dt, steps, work64, "fp64", graph)
+    del work64
     rows = []
     for prec in ("fp32", "mixf32", "bf16x3", "f16x2"):
         ty = torch.float32 if prec == "fp32" else torch.float64
@@ -551,7 +556,7 @@ def main():
     }
     out["graph"] = not args.no_graph
     if not args.no_extra and prec == "fp64" and not args.n and args.mesh == "box":
-        out["mixed"] = mixed_variants(m, w_start, w, dt, args.steps, gpu_s, ty,
+        out["mixed"] = mixed_variants(m, w_start, dt, STUDY_STEPS[args.config],
                                       not args.no_graph)
         if args.config != "c4":
             out["c4_fp64"] = c4_rate(dg, not args.no_graph)

@@ -124,33 +124,50 @@ class Space:
         from outside the domain) take the outer values from wb (and the outer convecting
         velocity from ub in frozen mode, from wb in self mode), given at boundary_points();
         the flux formula is the interior one with these outer values."""
+        elems = np.arange(self.mesh.E) if elems is None else np.asarray(elems)
+        out = np.empty((len(elems), self.dim, self.np))
+        for s in range(0, len(elems), self.chunk):
+            vol, facs = self._terms(w, u, elems[s:s + self.chunk], wb, ub)
+            fac = np.zeros_like(vol)
+            for ff in facs:
+                fac += ff
+            out[s:s + self.chunk] = vol + fac
+        return out
+
+    def form_parts(self, w, u=None, elems=None, wb=None, ub=None):
+        """The terms of C_h(u; w, phi_{T,i,m}) (Sec. 2.3) separately: the volume term
+        -int_T (w (x) u) : grad phi [n, d, Np] and the facet terms int_F (u.n) w^ phi of the
+        local facets F [d+1, n, d, Np]; form() is their sum."""
+        elems = np.arange(self.mesh.E) if elems is None else np.asarray(elems)
+        parts = [self._terms(w, u, elems[s:s + self.chunk], wb, ub)
+                 for s in range(0, len(elems), self.chunk)]
+        return (np.concatenate([p[0] for p in parts]),
+                np.concatenate([np.stack(p[1]) for p in parts], axis=1))
+
+    def _terms(self, w, u, T, wb, ub):
+        """Volume term and the list of facet terms of C_h on the elements T (one chunk)."""
         m, d = self.mesh, self.dim
         uu = w if u is None else u
         ubb = wb if u is None else ub
-        elems = np.arange(m.E) if elems is None else np.asarray(elems)
-        out = np.empty((len(elems), d, self.np))
-        for s in range(0, len(elems), self.chunk):
-            T = elems[s:s + self.chunk]
-            # volume term: - int_T w_i u_j d_j phi_m dx
-            wq = np.einsum("qm,tim->tqi", self.phi_v, w[T])
-            uq = np.einsum("qm,tim->tqi", self.phi_v, uu[T])
-            grad = np.einsum("tkj,qmk->tqmj", m.Jinv[T], self.dphi_v)  # physical gradients
-            conv = np.einsum("tqj,tqmj->tqm", uq, grad)  # u . grad phi_m
-            vol = -np.einsum("t,q,tqi,tqm->tim", m.absdetJ[T], self.vw, wq, conv)
-            # facet term: int_dT (u.n) w^ phi_m ds with the pointwise upwind value
-            pown, pnbr = self.facet_basis(T)
-            fac = np.zeros_like(vol)
-            for f in range(d + 1):
-                wm = np.einsum("tqm,tim->tqi", pown[:, f], w[T])
-                wp = self._outer(T, f, pnbr, w, wb)
-                um = np.einsum("tqm,tim->tqi", pown[:, f], uu[T])
-                up = self._outer(T, f, pnbr, uu, ubb)
-                beta = 0.5 * np.einsum("tqj,tj->tq", um + up, m.normal[T, f])
-                what = np.where(beta[..., None] > 0.0, wm, wp)
-                fac += np.einsum("t,q,tq,tqi,tqm->tim", m.area[T, f], self.fw, beta, what,
-                                 pown[:, f])
-            out[s:s + self.chunk] = vol + fac
-        return out
+        # volume term: - int_T w_i u_j d_j phi_m dx
+        wq = np.einsum("qm,tim->tqi", self.phi_v, w[T])
+        uq = np.einsum("qm,tim->tqi", self.phi_v, uu[T])
+        grad = np.einsum("tkj,qmk->tqmj", m.Jinv[T], self.dphi_v)  # physical gradients
+        conv = np.einsum("tqj,tqmj->tqm", uq, grad)  # u . grad phi_m
+        vol = -np.einsum("t,q,tqi,tqm->tim", m.absdetJ[T], self.vw, wq, conv)
+        # facet terms: int_F (u.n) w^ phi_m ds with the pointwise upwind value
+        pown, pnbr = self.facet_basis(T)
+        facs = []
+        for f in range(d + 1):
+            wm = np.einsum("tqm,tim->tqi", pown[:, f], w[T])
+            wp = self._outer(T, f, pnbr, w, wb)
+            um = np.einsum("tqm,tim->tqi", pown[:, f], uu[T])
+            up = self._outer(T, f, pnbr, uu, ubb)
+            beta = 0.5 * np.einsum("tqj,tj->tq", um + up, m.normal[T, f])
+            what = np.where(beta[..., None] > 0.0, wm, wp)
+            facs.append(np.einsum("t,q,tq,tqi,tqm->tim", m.area[T, f], self.fw, beta, what,
+                                  pown[:, f]))
+        return vol, facs
 
     def apply(self, w, u=None, elems=None, wb=None, ub=None):
         """r = -(M^V)^-1 C^V(u) w on elements `elems` (all by default); u=None means u := w.

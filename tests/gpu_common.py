@@ -45,6 +45,50 @@ def initial_state(sp, field="tg", seed=0, sd=1e-3, chunk=65536):
     return out + synth.noise(sp.shape, seed=seed, sd=sd)
 
 
+# Reduced-precision variants: unit roundoff of their basis contractions (FP32 coefficients,
+# tables and sums; two FP16 pieces carry 22 significant bits; three BF16 pieces hold the FP32
+# value exactly and the cross products they drop lie below 2^-24)
+UNIT = {"fp32": 2.0 ** -24, "mixf32": 2.0 ** -24, "f16x2": 2.0 ** -22, "bf16x3": 2.0 ** -24}
+
+
+def operator_scales(sp, w, u=None, elems=None, wb=None, ub=None):
+    """(r, amp, rate) from the oracle: r = -(M^V)^-1 C_h(u; w, .) on `elems` (all by default),
+    amp = (|vol| + sum_F |fac_F|) / |r|, how much larger the volume term and the facet terms of
+    C_h (Sec. 2.3) are than their sum, and rate = |r| / |w|; L2 norms with the element
+    measures."""
+    elems = np.arange(sp.mesh.E) if elems is None else np.asarray(elems)
+    vol, facs = sp.form_parts(w, u, elems, wb, ub)
+    mass = sp.mass[elems][:, None, :]
+    J = sp.mesh.absdetJ[elems]
+    l2 = lambda a: float(np.sqrt(np.einsum("t,tim->", J, a * a)))
+    fac = np.zeros_like(vol)
+    for ff in facs:  # the order of form()
+        fac += ff
+    r = -(vol + fac) / mass
+    terms = l2(vol / mass) + sum(l2(ff / mass) for ff in facs)
+    return r, terms / l2(r), l2(r) / l2(w[elems])
+
+
+def reduced_bars(prec, amp, inc=0.0, n=0, tol=1e-12):
+    """(apply bar, bar of the state after n substeps) for a result of precision variant `prec`
+    against the FP64 oracle, in relative L2.
+
+    FP64: the parity bar tol.  Reduced precision: every contraction rounds at the unit
+    roundoff u of UNIT, so the volume and the facet term of the operator each carry an error
+    of about u times their size, and r, their difference, a relative error of about u amp
+    (amp from operator_scales).  A substep adds dt r, of relative size inc = dt |r| / |w|, so
+    n substeps carry about n u amp inc, plus the rounding of an FP32 state, s = 2^-24.
+    Measured on MI355X over the parity cases (2D and 3D, periodic, bounded and one-cell meshes,
+    self and frozen mode, full-size workloads): 0.4 to 3.5 u amp after one application,
+    whatever the variant and the contraction length (the FP16 pairs at the low end); after
+    substeps 0.25 to 1.2 of n u amp inc + s.  The bars are 5 u amp and 3 (n u amp inc + s)."""
+    if prec == "fp64":
+        return tol, tol
+    u = UNIT[prec]
+    s = 2.0 ** -24 if prec == "fp32" else 0.0
+    return 5 * u * amp, 3 * (n * u * amp * inc + s)
+
+
 def rel_l2(sp, a, b):
     """||a - b||_L2 / ||b||_L2 with the element measures (a, b coefficient arrays)."""
     J = sp.mesh.absdetJ

@@ -7,7 +7,7 @@ import os
 import numpy as np
 import pytest
 
-from gpu_common import initial_state, rel_l2, say
+from gpu_common import initial_state, operator_scales, reduced_bars, rel_l2, say
 from oracle.dg import Space, cfl_dt
 from oracle.mesh import box_mesh
 
@@ -33,9 +33,10 @@ def test_one_cell_meshes(dg, dim, k):
     sp = Space(box_mesh(dim, 1), k)
     w = initial_state(sp, seed=3, sd=0.1)
     u = initial_state(sp, field="fourier", seed=4)
-    for kern, prec, tol in [("valu", "fp64", 1e-12), ("mfma", "fp64", 1e-12),
-                            (None, "fp32", 1e-4), (None, "bf16x3", 1e-5),
-                            (None, "mixf32", 1e-5)]:
+    refs = {id(uu): operator_scales(sp, w, uu) for uu in (None, u)}
+    # bars: gpu_common.reduced_bars
+    for kern, prec in [("valu", "fp64"), ("mfma", "fp64"), (None, "fp32"), (None, "bf16x3"),
+                       (None, "f16x2"), (None, "mixf32")]:
         if kern:
             os.environ["DGCONV_FP64_KERNEL"] = kern
         else:
@@ -45,10 +46,12 @@ def test_one_cell_meshes(dg, dim, k):
         for uu in (None, u):
             got = m.apply(dev(w, ty), None if uu is None else dev(uu, ty),
                           precision=prec).double().cpu().numpy()
-            ref = sp.apply(w, uu)
+            ref, amp, _ = refs[id(uu)]
             e = rel_l2(sp, got, ref)
-            say("   %s %s %s: %.3e" % (kern, prec, "frozen" if uu is not None else "self", e))
-            assert e <= (tol if prec == "fp64" else 100 * tol)
+            bar = reduced_bars(prec, amp)[0]
+            say("   %s %s %s: %.3e (bar %.1e)" % (kern, prec, "frozen" if uu is not None else "self",
+                                                e, bar))
+            assert e <= bar
     os.environ.pop("DGCONV_FP64_KERNEL", None)
 
 

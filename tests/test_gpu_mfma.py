@@ -3,19 +3,17 @@
 * FP64 on the matrix cores (v_mfma_f64_16x16x4): the same 1e-12 relative L2 bar as the VALU
   path.
 * Mixed precision (FP64 state, flux, facet sums and RK; basis contractions as split FP16x2 or
-  BF16x3 products with FP32 accumulation): the error against the FP64 oracle is measured and
-  held below a bound derived from the pieces' precision: two FP16 pieces carry 22 significant
-  bits and three BF16 pieces 24, so each contraction entry carries a relative error of about
-  2^-22 (2.4e-7) or 2^-24 (6e-8) plus FP32 accumulation over 16 terms; the operator amplifies
-  relative errors of its volume and facet terms by their cancellation (~1/(2 pi h)).  The
-  bounds below are 16x the resulting estimate.
+  BF16x3 products with FP32 accumulation, or FP32 on the vector units): the error against the
+  FP64 oracle is measured and held below the bars of gpu_common.reduced_bars (the pieces'
+  unit roundoff times the cancellation factor of the operator, which the oracle measures).
 """
 import os
 
 import numpy as np
 import pytest
 
-from gpu_common import C1, C5, initial_state, oracle_space, rel_l2, say
+from gpu_common import (C1, C5, UNIT, initial_state, operator_scales, oracle_space, reduced_bars,
+                        rel_l2, say)
 from oracle.dg import cfl_dt
 
 torch = pytest.importorskip("torch")
@@ -89,9 +87,6 @@ def test_fp64_mfma_c1_substeps(dg):
     assert e <= 1e-12
 
 
-BOUND = {"f16x2": 2.0 ** -22, "bf16x3": 2.0 ** -24}
-
-
 @pytest.mark.parametrize("prec", ["f16x2", "bf16x3"])
 @pytest.mark.parametrize("dim,k,N,jit", [(2, 2, 5, 0.2), (2, 4, 4, 0.0), (3, 2, 3, 0.15),
                                          (3, 3, 2, 0.0)])
@@ -101,63 +96,60 @@ def test_mixed_apply_error(dg, prec, dim, k, N, jit):
     m = lib_mesh(dg, sp, dim, N, k, jit, {})
     w = initial_state(sp, seed=1, sd=0.05)
     got = m.apply(dev(w), precision=prec).cpu().numpy()
-    ref = sp.apply(w)
+    ref, amp, _ = operator_scales(sp, w)
     e = rel_l2(sp, got, ref)
-    amp = 1.0 / (2 * np.pi * (1.0 / N))
-    bound = 16 * BOUND[prec] * amp * 4
-    say("   rel_l2 %.3e (bound %.1e)" % (e, bound))
-    assert e <= bound
+    bar = reduced_bars(prec, amp)[0]
+    say("   rel_l2 %.3e (bar %.1e, %.2f u amp)" % (e, bar, e / (UNIT[prec] * amp)))
+    assert e <= bar
 
 
-@pytest.mark.parametrize("prec", ["f16x2", "bf16x3"])
-def test_mixed_c5_substeps(dg, prec):
+def c5_apply_and_substeps(dg, prec, n=4):
+    """The 2D 128^2 x 2 P3 workload (random Fourier field): one application and n substeps of
+    variant prec against the oracle, with their bars (gpu_common.reduced_bars)."""
     dim, N, k = C5
-    say("case mixed %s c5 apply + 4 substeps" % prec)
     sp = oracle_space(dim, N, k)
     m = dg.Mesh.box(dim, N, k)
     w = initial_state(sp, field="fourier", seed=3)
     r = m.apply(dev(w), precision=prec).cpu().numpy()
-    e_apply = rel_l2(sp, r, sp.apply(w))
+    ref, amp, rate = operator_scales(sp, w)
+    e_apply = rel_l2(sp, r, ref)
     dt = cfl_dt(1.0 / N, k, sp.max_speed(w))
     wd = dev(w)
-    m.rk_substeps(wd, dt, 4, precision=prec)
-    e_state = rel_l2(sp, wd.cpu().numpy(), sp.ssprk3(w, dt, 4))
-    say("   apply rel_l2 %.3e  state after 4 substeps rel_l2 %.3e" % (e_apply, e_state))
-    amp = 1.0 / (2 * np.pi / N)
-    assert e_apply <= 64 * BOUND[prec] * amp
-    assert e_state <= 1e-6
+    m.rk_substeps(wd, dt, n, precision=prec)
+    e_state = rel_l2(sp, wd.cpu().numpy(), sp.ssprk3(w, dt, n))
+    b_apply, b_state = reduced_bars(prec, amp, dt * rate, n=n)
+    say("   apply rel_l2 %.3e (bar %.1e)  state after %d substeps rel_l2 %.3e (bar %.1e)"
+        % (e_apply, b_apply, n, e_state, b_state))
+    assert e_apply <= b_apply
+    assert e_state <= b_state
+
+
+@pytest.mark.parametrize("prec", ["f16x2", "bf16x3"])
+def test_mixed_c5_substeps(dg, prec):
+    say("case mixed %s c5 apply + 4 substeps" % prec)
+    c5_apply_and_substeps(dg, prec)
 
 
 @pytest.mark.parametrize("dim,k,N,jit", CASES)
 def test_mixf32_apply_all_degrees(dg, dim, k, N, jit):
     """FP64 state, flux, facet sums and update around FP32 contractions (the vector-unit
-    kernel), self and frozen mode, every compiled degree, against the FP64 oracle.  Bar: the
-    FP32 contraction model of test_gpu_parity.full_bars (16 u / (2 pi h), u = 2^-24)."""
+    kernel), self and frozen mode, every compiled degree, against the FP64 oracle (bars:
+    gpu_common.reduced_bars)."""
     say("case mixf32 apply dim=%d k=%d" % (dim, k))
     sp = oracle_space(dim, N, k, jit, seed=k)
     m = lib_mesh(dg, sp, dim, N, k, jit, {})
     w = initial_state(sp, seed=1, sd=0.05)
     u = initial_state(sp, field="fourier", seed=2)
-    bar = 16 * 2.0 ** -24 * max(1.0, N / (2 * np.pi))
     for uu in (None, u):
         got = m.apply(dev(w), None if uu is None else dev(uu), precision="mixf32").cpu().numpy()
-        e = rel_l2(sp, got, sp.apply(w, uu))
-        say("   %s rel_l2 %.3e (bar %.1e)" % ("frozen" if uu is not None else "self", e, bar))
+        ref, amp, _ = operator_scales(sp, w, uu)
+        e = rel_l2(sp, got, ref)
+        bar = reduced_bars("mixf32", amp)[0]
+        say("   %s rel_l2 %.3e (bar %.1e, %.2f u amp)"
+            % ("frozen" if uu is not None else "self", e, bar, e / (UNIT["mixf32"] * amp)))
         assert e <= bar
 
 
 def test_mixf32_c5_substeps(dg):
-    dim, N, k = C5
     say("case mixf32 c5 apply + 4 substeps")
-    sp = oracle_space(dim, N, k)
-    m = dg.Mesh.box(dim, N, k)
-    w = initial_state(sp, field="fourier", seed=3)
-    r = m.apply(dev(w), precision="mixf32").cpu().numpy()
-    e_apply = rel_l2(sp, r, sp.apply(w))
-    dt = cfl_dt(1.0 / N, k, sp.max_speed(w))
-    wd = dev(w)
-    m.rk_substeps(wd, dt, 4, precision="mixf32")
-    e_state = rel_l2(sp, wd.cpu().numpy(), sp.ssprk3(w, dt, 4))
-    say("   apply rel_l2 %.3e  state after 4 substeps rel_l2 %.3e" % (e_apply, e_state))
-    assert e_apply <= 16 * 2.0 ** -24 * N / (2 * np.pi)
-    assert e_state <= 1e-6
+    c5_apply_and_substeps(dg, "mixf32")

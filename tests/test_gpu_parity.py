@@ -6,8 +6,8 @@ Every test prints its case before touching the GPU.
 import numpy as np
 import pytest
 
-from gpu_common import (C1, C2, C3, C4, C5, initial_state, oracle_rk_on_sample, oracle_space,
-                        rel_l2, rel_l2_rows, say)
+from gpu_common import (C1, C2, C3, C4, C5, initial_state, operator_scales, oracle_rk_on_sample,
+                        oracle_space, reduced_bars, rel_l2, rel_l2_rows, say)
 from oracle.dg import cfl_dt
 
 torch = pytest.importorskip("torch")
@@ -108,15 +108,15 @@ def full_case(cfg, field):
         rng = np.random.default_rng(7)
         sample = np.unique(np.concatenate([rng.choice(sp.mesh.E, 300, replace=False),
                                            [0, sp.mesh.E - 1]]))
-        ref_apply = sp.apply(w, elems=sample)
+        ref_apply, amp, rate = operator_scales(sp, w, elems=sample)
         dt = cfl_dt(1.0 / N, k, 3.0)  # any positive step: a bound on max|w| for these fields
+        inc = dt * rate  # one step's increment relative to the state
         S, ref_rk = oracle_rk_on_sample(sp, w, dt, sample[:60])
-        _FULL[key] = (sp, w, sample, ref_apply, dt, S, ref_rk)
+        _FULL[key] = (sp, w, sample, ref_apply, dt, S, ref_rk, amp, inc)
     return _FULL[key]
 
 
-# (configuration, field, precision, apply bar, substep bar); the FP64 bars are the parity bar,
-# the others are derived in test_full_size_sampled's docstring
+# (configuration, field, precision)
 FULL_CASES = [
     (C2, "tg", "fp64"), (C2, "tg", "fp32"),
     (C3, "tg", "fp64"), (C3, "tg", "f16x2"), (C3, "tg", "bf16x3"),
@@ -125,36 +125,17 @@ FULL_CASES = [
 ]
 
 
-def full_bars(prec, cfg):
-    """(apply bar, substep bar) for relative L2 over the sampled elements.
-
-    FP64: the parity bar.  Lower precisions: a contraction rounded at unit roundoff u (FP32
-    operands and sums: 2^-24; the split pieces: 2^-22 for two FP16 pieces, 2^-24 for three
-    BF16 pieces) perturbs the volume and facet terms by about u times their size; the operator
-    is their difference, smaller by the cancellation factor ~ 2 pi h (the fields' wavelength
-    is the box), so r carries a relative error of about u / (2 pi h).  The bar is 16 times
-    that.  After one substep the error is dt r's, relative to the state: smaller by dt |r| / |w|
-    ~ 0.1 / k^2; an FP32 state adds its own rounding (2^-24 relative), so its substep bar is
-    16 (2^-24 + 0.1 u / (2 pi h k^2))."""
-    dim, N, k = cfg
-    if prec == "fp64":
-        return TOL, TOL
-    u = {"fp32": 2.0 ** -24, "mixf32": 2.0 ** -24, "f16x2": 2.0 ** -22, "bf16x3": 2.0 ** -24}[prec]
-    amp = N / (2 * np.pi)
-    state = 2.0 ** -24 if prec == "fp32" else 0.0
-    return 16 * u * amp, 16 * (state + 0.1 * u * amp / k ** 2)
-
-
 @pytest.mark.parametrize("cfg,field,prec", FULL_CASES)
 def test_full_size_sampled(dg, cfg, field, prec):
     """Full-size meshes: one apply and one fused SSP-RK3 substep (the benchmark launch
     configuration), checked on sampled elements the oracle evaluates one by one, for the FP64
     path and for the FP32, FP32-contraction and split-product variants the configurations name
-    (bars: full_bars)."""
+    (bars: gpu_common.reduced_bars, with the cancellation factor measured on the sample)."""
     dim, N, k = cfg
     say("case full-size sampled dim=%d N=%d k=%d %s" % (dim, N, k, prec))
-    sp, w, sample, ref, dt, S, ref1 = full_case(cfg, field)
-    bar_apply, bar_rk = full_bars(prec, cfg)
+    sp, w, sample, ref, dt, S, ref1, amp, inc = full_case(cfg, field)
+    bar_apply, bar_rk = reduced_bars(prec, amp, inc, n=1, tol=TOL)
+    say("   cancellation factor %.1f, step increment %.2e" % (amp, inc))
     ty = torch.float32 if prec == "fp32" else torch.float64
     m = dg.Mesh.box(dim, N, k)
     wd = dev(w, ty)
@@ -217,20 +198,19 @@ def test_deterministic_and_stream(dg):
 
 
 def test_fp32_path(dg):
-    """FP32 state and arithmetic against the FP64 oracle.
-
-    Bound: FP32 unit roundoff 6e-8, times the cancellation of the operator (volume and facet
-    terms are ~1/(2 pi h) ~ 20 times larger than their sum at h = 1/128), times the growth
-    over ~10^2 accumulated products (~10), times a safety factor of 8: 1e-4."""
+    """FP32 state and arithmetic against the FP64 oracle on the 2D 128^2 x 2 P3 workload (bar:
+    gpu_common.reduced_bars)."""
     dim, N, k = C5
     say("case fp32 c5")
     sp = oracle_space(dim, N, k)
     m = dg.Mesh.box(dim, N, k)
     w = initial_state(sp, field="fourier", seed=3)
+    ref, amp, _ = operator_scales(sp, w)
+    bar = reduced_bars("fp32", amp)[0]
     r = m.apply(dev(w, torch.float32), precision="fp32").double().cpu().numpy()
-    e = rel_l2(sp, r, sp.apply(w))
-    say("   fp32 apply rel_l2 %.3e" % e)
-    assert e < 1e-4
+    e = rel_l2(sp, r, ref)
+    say("   fp32 apply rel_l2 %.3e (bar %.1e, %.1f u amp)" % (e, bar, e / (2.0 ** -24 * amp)))
+    assert e <= bar
 
 
 def test_argument_errors(dg):

@@ -8,7 +8,7 @@ import os
 import numpy as np
 import pytest
 
-from gpu_common import initial_state, rel_l2, say
+from gpu_common import initial_state, operator_scales, reduced_bars, rel_l2, say
 from oracle.dg import Space, cfl_dt
 from oracle.mesh import Mesh, box_mesh
 
@@ -55,8 +55,8 @@ def test_shuffled_frames_vs_oracle(dg, dim, k, N, per):
         ub = 0.5 * wb
     else:
         wb = ub = None
-    ref_self = sp.apply(w, wb=wb)
-    ref_frozen = sp.apply(w, u, wb=wb, ub=ub)
+    ref_self, amp_s, rate = operator_scales(sp, w, wb=wb)
+    ref_frozen, amp_f, _ = operator_scales(sp, w, u, wb=wb, ub=ub)
     dt = cfl_dt(1.0 / N, k, sp.max_speed(w))
     ref_rk = sp.ssprk3(w, dt, 2, wb=wb)
     E = om.E
@@ -79,7 +79,10 @@ def test_shuffled_frames_vs_oracle(dg, dim, k, N, per):
             e = [rel_l2(sp, r1.double().cpu().numpy(), ref_self),
                  rel_l2(sp, r2.double().cpu().numpy(), ref_frozen),
                  rel_l2(sp, W.double().cpu().numpy(), ref_rk)]
-            say("      self %.3e  frozen %.3e  substeps %.3e" % tuple(e))
-            tol = 1e-12 if prec == "fp64" else 1e-4
-            assert max(e) <= tol, (lane, prec, e)
+            # bars: gpu_common.reduced_bars
+            b1, b3 = reduced_bars(prec, amp_s, dt * rate, n=2)
+            b = [b1, reduced_bars(prec, amp_f)[0], b3]
+            say("      self %.3e  frozen %.3e  substeps %.3e" % tuple(e)
+                + "  (bars %.1e %.1e %.1e)" % tuple(b))
+            assert all(x <= y for x, y in zip(e, b)), (lane, prec, e, b)
     os.environ.pop("DGCONV_LANE_TABLES", None)
