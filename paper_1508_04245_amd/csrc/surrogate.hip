@@ -45,10 +45,21 @@ __device__ __forceinline__ float gelu_d(float z) {
          z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
+// v_mfma_f32_16x16x32_bf16: BF16 operands, K = 32 per instruction (lane l holds the 8 K
+// values at 8 (l / 16) of its row of A and its column of B)
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f4 mfma32(const s8& a, const s8& b, f4 acc) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, a), __builtin_bit_cast(b8, b),
+                                                 acc, 0, 0, 0);
+}
+
 // ------------------------------------------------------------------ GEMM
-// C(m,n) = sum_k A(m,k) B(k,n) over BF16 operands with FP32 accumulation on the matrix cores
-// (v_mfma_f32_16x16x16_bf16).  A(m,k) = A[m am + k ak], B(k,n) = B[k bk + n bn].  A wave
-// computes a 32x32 block (2x2 MFMA tiles), a workgroup of 4 waves a 64x64 block.
+// C(m,n) = sum_k A(m,k) B(k,n) over BF16 operands with FP32 accumulation on the matrix cores.
+// A(m,k) = A[m am + k ak], B(k,n) = B[k bk + n bn].  General strides (the backward products,
+// gathered element by element): v_mfma_f32_16x16x16_bf16, a wave computing a 32 x 64 block.
+// Operands contiguous along K (the forward layers): the LDS-tiled kernel below.
 enum Epi { EPI_BIAS = 0, EPI_BIAS_GELU = 1, EPI_GELU_BWD = 2, EPI_STORE = 3 };
 struct GemmArgs {
   int M, N, K;
@@ -136,11 +147,12 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
 }
 
 // Tiled GEMM for operands contiguous along K (A(m,k) = A[m am + k], B(k,n) = B[n bn + k]: the
-// forward layers, y = x W^T).  Workgroup tile 128 x 128, K step 32; both operand tiles go
+// forward layers, y = x W^T).  Workgroup tile 128 x 128, K step 32 (one K = 32 instruction per
+// output tile and step); both operand tiles go
 // through LDS (16-byte global loads, double buffered: the next step's loads are in flight
 // during the current step's matrix instructions); 4 waves, each 64 x 64 (4 x 4 MFMA tiles).
-// LDS rows are padded to 40 elements (80 bytes) so the 8-byte operand reads of the 16 rows
-// of a tile fall in distinct banks.
+// LDS rows are padded to 40 elements (80 bytes) so the 16-byte operand reads of the 16 rows
+// of a tile spread over the banks.
 constexpr int kTBM = 128, kTBN = 128, kTBK = 32, kTLD = kTBK + 8;
 
 template <int EPI>
@@ -184,18 +196,17 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
   for (int it = 0; it < nk; ++it) {
     const int buf = it & 1;
     if (it + 1 < nk) gload((it + 1) * kTBK);
+    {
+      // one K = 32 step: lane l's 8 K values at 8 (l / 16) on both operands
+      s8 a[4], b[4];
 #pragma unroll
-    for (int ks = 0; ks < kTBK; ks += 16) {
-      s4 a[4], b[4];
+      for (int i = 0; i < 4; ++i) a[i] = *(const s8*)(&sa[buf][(wm + 16 * i + c) * kTLD + 8 * g4]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = *(const s4*)(&sa[buf][(wm + 16 * i + c) * kTLD + ks + 4 * g4]);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = *(const s4*)(&sb[buf][(wn + 16 * j + c) * kTLD + ks + 4 * g4]);
+      for (int j = 0; j < 4; ++j) b[j] = *(const s8*)(&sb[buf][(wn + 16 * j + c) * kTLD + 8 * g4]);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma32(a[i], b[j], acc[i][j]);
     }
     // buf ^ 1 was last read in step it - 1, which every wave finished before the barrier
     if (it + 1 < nk) sstore(buf ^ 1);
@@ -224,6 +235,103 @@ hipError_t gemm(const GemmArgs& g, hipStream_t s) {
     hipLaunchKernelGGL(gemm_kernel<EPI>, grid, dim3(256), 0, s, g);
   }
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ fused inference
+// The whole network for a block of kRB rows in one workgroup (inference: no pre-activations
+// are kept).  The inputs and each layer's activations stay in LDS as BF16; the weights are
+// read from L2 (the BF16 copy, every block reads each layer once).  Layers 1-3: wave w
+// computes columns [64 w, 64 w + 64) of all kRB rows as 4 x 4 tiles of v_mfma_f32_16x16x32_bf16
+// (K = 32 per instruction, the operands' 8 K values of lane l at 8 (l / 16)); the activation
+// overwrites the layer's input in place once every wave has finished reading it.  Layer 4:
+// wave w computes rows [16 w, 16 w + 16) of the 20 outputs (two 16-column tiles).  LDS rows
+// are padded by 8 elements so that the 16-byte operand reads of a tile's 16 rows spread over
+// the banks.
+constexpr int kRB = 64;                    // rows per workgroup
+constexpr int kXLD = 96 + 8, kHLD = kHid + 8;
+
+// 8 BF16 values of row n of a weight matrix [*, fin] at columns k .. k + 7 (zero beyond fin;
+// fin is a multiple of 8)
+__device__ __forceinline__ s8 wload8(const uint16_t* W, int fin, int n, int k) {
+  if (k >= fin) return s8{0, 0, 0, 0, 0, 0, 0, 0};
+  return __builtin_bit_cast(s8, *(const uint4*)(W + (int64_t)n * fin + k));
+}
+
+__global__ void __launch_bounds__(256) mlp_fused_kernel(int64_t B, const uint16_t* __restrict__ xb,
+                                                        const uint16_t* __restrict__ wbf,
+                                                        const float* __restrict__ master,
+                                                        float* __restrict__ y) {
+  __shared__ __attribute__((aligned(16))) uint16_t sx[kRB * kXLD];
+  __shared__ __attribute__((aligned(16))) uint16_t sh[kRB * kHLD];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * kRB;
+  // inputs: kRB rows of 80 BF16 values (10 chunks of 8), zero padding to 96 and beyond B
+  for (int q = t; q < kRB * 12; q += 256) {
+    const int row = q / 12, ch = q % 12;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (ch < kIn / 8 && r0 + row < B) v = *(const uint4*)(xb + (r0 + row) * kIn + 8 * ch);
+    *(uint4*)(&sx[row * kXLD + 8 * ch]) = v;
+  }
+  __syncthreads();
+  const int n0 = 64 * w;
+  for (int l = 0; l < 3; ++l) {
+    const int fin = kFanIn[l];
+    const uint16_t* W = wbf + kOffW[l];
+    const float* bias = master + kOffW[l] + (int64_t)kHid * fin;
+    const uint16_t* src = l == 0 ? sx : sh;
+    const int ld = l == 0 ? kXLD : kHLD;
+    f4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = f4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < fin; k0 += 32) {
+      s8 a[4], b[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = wload8(W, fin, n0 + 16 * j + c, k0 + 8 * g);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = *(const s8*)(&src[(16 * i + c) * ld + k0 + 8 * g]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma32(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();  // every wave has read the layer's input
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + 16 * j + c;
+      const float bn = bias[n];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sh[(16 * i + 4 * g + r) * kHLD + n] = f2bf(gelu(acc[i][j][r] + bn));
+    }
+    __syncthreads();
+  }
+  // output layer: rows [16 w, 16 w + 16), columns 0 .. 19 of two 16-column tiles
+  const uint16_t* W = wbf + kOffW[3];
+  const float* bias = master + kOffW[3] + (int64_t)kOut * kHid;
+  f4 acc[2] = {f4{0, 0, 0, 0}, f4{0, 0, 0, 0}};
+  for (int k0 = 0; k0 < kHid; k0 += 32) {
+    const s8 a = *(const s8*)(&sh[(16 * w + c) * kHLD + k0 + 8 * g]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = 16 * j + c;
+      const s8 b = n < kOut ? wload8(W, kHid, n, k0 + 8 * g) : s8{0, 0, 0, 0, 0, 0, 0, 0};
+      acc[j] = mfma32(a, b, acc[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int n = 16 * j + c;
+    if (n >= kOut) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + 16 * w + 4 * g + r;
+      if (row < B) y[row * kOut + n] = acc[j][r] + bias[n];
+    }
+  }
 }
 
 // ------------------------------------------------------------------ elementwise / reductions
@@ -454,8 +562,14 @@ dg_status ensure_cap(dg_surrogate* s, int64_t B) {
   return DG_OK;
 }
 
-// forward over s->xb (BF16 inputs) for B rows; keeps pre-activations when train
+// forward over s->xb (BF16 inputs) for B rows into s->y; with train, layer by layer keeping the
+// pre-activations and activations for the backward pass, else in one fused launch
 dg_status forward(dg_surrogate* s, int64_t B, bool train, hipStream_t st) {
+  if (!train) {
+    hipLaunchKernelGGL(mlp_fused_kernel, dim3(nblk(B, kRB)), dim3(256), 0, st, B, s->xb, s->wbf,
+                       s->master, s->y);
+    return hipGetLastError() == hipSuccess ? DG_OK : fail(DG_EDEVICE, "mlp_fused_kernel launch");
+  }
   const uint16_t* in = s->xb;
   int fin = kIn;
   for (int l = 0; l < 3; ++l) {

@@ -8,7 +8,7 @@ evaluated on unseen seeds (10001..10004) from states of the plain trajectory:
 * acceptance rate of the a-posteriori check at tol = 2x the plain method's own median
   trapezoid defect;
 * time per macro-step (network path, every candidate accepted) against the 8 plain substeps,
-  HIP events on one stream;
+  HIP events on one stream, and the network's forward pass alone over every element;
 * error of the network's increment against the plain judge, beside the two baselines of the
   same cost class: forward Euler over tau = M dt and one SSP-RK3 step of size tau.
 
@@ -75,6 +75,19 @@ def test_trained_macro_step_gain():
     torch.cuda.synchronize()
     t_plain = ev[0].elapsed_time(ev[1]) / reps
     t_net = ev[2].elapsed_time(ev[3]) / reps
+    # the network alone on every element (inputs of w0), the inference path of the macro-step
+    scale = mesh.reduce("maxvel", w0)[:1].contiguous()
+    xin = sur.features(w0, scale)
+    for _ in range(3):
+        sur.forward(xin)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        sur.forward(xin)
+    ev[1].record()
+    torch.cuda.synchronize()
+    t_mlp = ev[0].elapsed_time(ev[1]) / reps
+    mlp_flops = 2.0 * (80 * 256 + 2 * 256 * 256 + 256 * 20) * mesh.E
     acc_rate = res["accepted"] / res["macro_steps"]
     out = {"study": "macro-step gain", "workload": "2D periodic 128x128x2 triangles, P3, M=8",
            "train_samples": int(X.shape[0]), "loss_first": hist[0][1], "loss_last": hist[-1][1],
@@ -85,6 +98,8 @@ def test_trained_macro_step_gain():
            "err_increment_euler_median": float(np.median(probe["err_increment_euler"])),
            "err_increment_rk3_coarse_median": float(np.median(probe["err_increment_rk3_coarse"])),
            "ms_plain_8_substeps": t_plain, "ms_network_macro_step": t_net,
+           "ms_network_forward_all_elements": t_mlp,
+           "network_forward_tflops": mlp_flops / (t_mlp * 1e-3) / 1e12,
            "speedup_if_all_accepted": t_plain / t_net,
            "speedup_at_measured_acceptance": t_plain / (t_net + (1 - acc_rate) * t_plain)}
     say("   " + json.dumps(out))

@@ -71,7 +71,12 @@ def test_forward_and_gradient_vs_oracle(env):
     e = rel(y, yref)
     say("   forward rel %.3e" % e)
     assert e < 3e-2
+    # the fused inference kernel against the layer-by-layer training forward (the same BF16
+    # activations; the two differ only in the order of the FP32 accumulation)
     loss, g = sur.grad(xd, td)
+    l_fused = float(np.mean((y.astype(np.float64) - t) ** 2))
+    say("   fused-forward loss %.6f, training-forward loss %.6f" % (l_fused, loss.item()))
+    assert abs(l_fused - loss.item()) <= 1e-3 * loss.item()
     lref, gref = mlp.loss_and_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
     g = g.cpu().numpy().astype(np.float64)
     cos = float(g @ gref / np.linalg.norm(g) / np.linalg.norm(gref))
