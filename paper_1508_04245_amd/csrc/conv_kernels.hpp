@@ -536,4 +536,219 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
   }
 }
 
+// FP64 self-convection on a periodic mesh with tiles of one element class (the workloads'
+// default path): the same arithmetic as conv_kernel<D, K, double, true, SM, false, false>, with
+// the volume loop cut into D + 2 pieces and the facets between them.  The neighbour state of
+// each facet is requested before the volume piece that precedes it, so its memory latency
+// overlaps that piece (the registers of one neighbour state are free during the volume loop),
+// and the volume and facet terms accumulate into one set of sums.
+template <int D, int K, int SM>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(min_waves<D, K, double>(), 8))) conv_self_kernel(ConvArgs<double> A) {
+  using S = Shape<D, K>;
+  using T = double;
+  constexpr int NP = S::NP;
+  typedef const int __attribute__((address_space(4)))* ciptr;
+  const int lane = threadIdx.x & 63;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int tile = __builtin_amdgcn_readfirstlane(blk * 4 + (threadIdx.x >> 6));
+  if (stopped(A.stop)) return;  // uniform over the grid
+  static_assert(SM == SM_ALL || staged_fits<D, K, T, SM>(), "staged tables exceed 64 KiB");
+  constexpr int LO = SM == SM_ALL ? 0 : staged_lo<D, K, SM>();
+  Tabs<SM, T, LO> tab;
+  tab.c = (typename Tabs<SM, T, LO>::cptr)A.tab;
+  if constexpr (SM != SM_ALL) {
+    __shared__ T stab[staged_hi<D, K, SM>() - LO];
+    stage_tables<D, K, SM>(stab, A.tab);
+    __syncthreads();
+    tab.l = stab;
+  } else {
+    tab.l = A.tab;
+  }
+  const int type = __builtin_amdgcn_readfirstlane(A.tile_type[tile]);
+  if (type < 0) {  // empty tile padding a block
+    if (A.mode == 2 && lane == 0) A.partial[tile] = 0.0;
+    return;
+  }
+  const int e_raw = A.elem_list[tile * 64 + lane];
+  const int e = e_raw >= 0 ? e_raw : A.elem_list[tile * 64];  // padded lanes redo lane 0
+  const ciptr ttab = (ciptr)A.type_tab;
+
+  T c[D][NP], ji[D][D], R[D][NP];
+  int nbv[D + 1];
+  {
+    const T* __restrict__ p = A.x + (size_t)e * D * NP;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int m = 0; m < NP; ++m) c[i][m] = p[i * NP + m];
+    const T* __restrict__ pj = A.jinv + (size_t)e * D * D;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) ji[i][j] = pj[i * D + j];
+#pragma unroll
+    for (int f = 0; f <= D; ++f) nbv[f] = A.nbr[(size_t)e * (D + 1) + f];
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int m = 0; m < NP; ++m) R[i][m] = T(0);
+
+  // neighbour state of the facet about to come
+  T cn[D][NP];
+  auto load_nbr_state = [&](int ne) {
+    const T* __restrict__ p = A.x + (size_t)ne * D * NP;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int m = 0; m < NP; ++m) cn[i][m] = p[i * NP + m];
+  };
+
+  // volume term over the points [q0, q1): R[i][m] += w_i(x_q) (J^-1 w(x_q)) . w_q grad^ phi_m
+  auto volume = [&](int q0, int q1) {
+#pragma unroll 1
+    for (int q = q0; q < q1; ++q) {
+      const int bq = S::OFF_BV + q * NP;
+      const int dq = S::OFF_DV + q * NP * D;
+      T wq[D], uh[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) wq[i] = T(0);
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        const T bm = tab.template get<TB_BV>(bq + m);
+#pragma unroll
+        for (int i = 0; i < D; ++i) wq[i] = fma(bm, c[i][m], wq[i]);
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        T s = T(0);
+#pragma unroll
+        for (int j = 0; j < D; ++j) s = fma(ji[a][j], wq[j], s);
+        uh[a] = s;
+      }
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        T P = T(0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) P = fma(uh[a], tab.template get<TB_DV>(dq + m * D + a), P);
+#pragma unroll
+        for (int i = 0; i < D; ++i) R[i][m] = fma(wq[i], P, R[i][m]);
+      }
+    }
+  };
+
+  // facet term of local facet f with the neighbour state in cn (pointwise upwind flux)
+  auto facet = [&](int f) {
+    const int tt = ttab[type * (D + 1) + f];
+    const int own = __builtin_amdgcn_readfirstlane(tt & 0xffff);
+    const int nbt = __builtin_amdgcn_readfirstlane(tt >> 16);
+    const int tro = S::OFF_TR + own * S::NFQ * NP;
+    const int trn = S::OFF_TR + nbt * S::NFQ * NP;
+    const int lfo = S::OFF_LF + own * S::NFQ * NP;
+    T Nt[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      T s = T(0);
+#pragma unroll
+      for (int a = 0; a < D; ++a) s = fma(ji[a][j], nref<D, T>(f, a), s);
+      Nt[j] = s;
+    }
+#pragma unroll 1
+    for (int q = 0; q < S::NFQ; ++q) {
+      T wm[D], wp[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) { wm[i] = T(0); wp[i] = T(0); }
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        const T to = tab.template get<TB_TRO>(tro + q * NP + m);
+        const T tn = tab.template get<TB_TRN>(trn + q * NP + m);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          wm[i] = fma(to, c[i][m], wm[i]);
+          wp[i] = fma(tn, cn[i][m], wp[i]);
+        }
+      }
+      // b = bb / 2;  F = b (wm + wp) / 2 + |b| (wm - wp) / 2
+      T bb = T(0);
+#pragma unroll
+      for (int j = 0; j < D; ++j) bb = fma(wm[j] + wp[j], Nt[j], bb);
+      const T hb = T(0.25) * bb;
+      const T ha = T(0.25) * fabs(bb);
+      T F[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) F[i] = hb * (wm[i] + wp[i]) + ha * (wm[i] - wp[i]);
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        const T l = tab.template get<TB_LF>(lfo + q * NP + m);
+#pragma unroll
+        for (int i = 0; i < D; ++i) R[i][m] = fma(-l, F[i], R[i][m]);
+      }
+    }
+  };
+
+  constexpr int NCH = D + 2;
+  load_nbr_state(nbv[0]);
+#pragma unroll
+  for (int f = 0; f <= D; ++f) {
+    volume(f * S::NQ / NCH, (f + 1) * S::NQ / NCH);
+    facet(f);
+    if (f < D) load_nbr_state(nbv[f + 1]);
+  }
+  volume((D + 1) * S::NQ / NCH, S::NQ);
+
+  T* o = A.out + (size_t)e * D * NP;
+  if (A.mode == 2) {
+    // every lane takes part in the wave sum; padded lanes store nothing and add zero
+    const T* pg = A.w0 + (size_t)e * D * NP;
+    T gv[D][NP];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int m = 0; m < NP; ++m) gv[i][m] = pg[i * NP + m];
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        const T res = fma(A.tau, R[i][m], gv[i][m] - c[i][m]);
+        if (e_raw >= 0) o[i * NP + m] = fma(A.ds, res, c[i][m]);
+        acc = fma(res, res, acc);
+      }
+    acc = wave_sum(e_raw >= 0 ? acc * A.absdet[e] : 0.0);
+    if (lane == 0) A.partial[tile] = acc;
+    return;
+  }
+  if (e_raw < 0) return;
+  if (A.mode == 0) {
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int m = 0; m < NP; ++m) o[i * NP + m] = R[i][m];
+  } else {
+    const T a = A.a, b = A.b, dt = A.dt;
+    if (a != T(0)) {
+      // all loads of w0 before any store: out may be w0 itself (in-place last stage), and
+      // back-to-back stores let whole cache lines complete in L2 before eviction
+      const T* pw = A.w0 + (size_t)e * D * NP;
+      T w0v[D][NP];
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int m = 0; m < NP; ++m) w0v[i][m] = pw[i * NP + m];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int m = 0; m < NP; ++m)
+          o[i * NP + m] = fma(a, w0v[i][m], b * fma(dt, R[i][m], c[i][m]));
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int m = 0; m < NP; ++m) o[i * NP + m] = b * fma(dt, R[i][m], c[i][m]);
+    }
+  }
+}
+
 }  // namespace dgk

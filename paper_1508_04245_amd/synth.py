@@ -16,6 +16,8 @@ Fields (all periodic on the unit box):
   * Shear wave (exact solution of w_t + div(w (x) w) = 0, div w = 0):
     w(x,t) = c + A sin(2 pi (xi.x - (xi.c) t)) eta, eta . xi = 0.
 """
+import os
+
 import numpy as np
 
 TWO_PI = 2.0 * np.pi
@@ -55,10 +57,37 @@ class FourierField:
         rms = np.sqrt(0.5 * np.sum(np.abs(a) ** 2))
         self.amp = a / rms
 
-    def __call__(self, x):
-        # Re sum_m a_m e^{i ph_m} = cos(ph) Re(a) - sin(ph) Im(a)
-        ph = TWO_PI * (x @ self.kappa.T)
-        return np.cos(ph) @ self.amp.real - np.sin(ph) @ self.amp.imag
+    def _eval(self, x):
+        # Re sum_m a_m e^{i ph_m} = cos(ph_m) Re(a_m) - sin(ph_m) Im(a_m), summed mode by mode
+        # with elementwise operations only (no BLAS call, so host threads may run it at once)
+        n, dim = x.shape
+        out = np.zeros((n, self.amp.shape[1]))
+        for m in range(self.kappa.shape[0]):
+            ph = x[:, 0] * self.kappa[m, 0]
+            for a in range(1, dim):
+                ph = ph + x[:, a] * self.kappa[m, a]
+            ph = TWO_PI * ph
+            c, s = np.cos(ph)[:, None], np.sin(ph)[:, None]
+            out += c * self.amp[m].real - s * self.amp[m].imag
+        return out
+
+    def __call__(self, x, chunk=1 << 18):
+        """The field at the points x [..., dim]; large inputs in chunks of points on host
+        threads (NumPy's elementwise loops release the GIL), each point evaluated alone."""
+        x = np.asarray(x, dtype=np.float64)
+        flat = x.reshape(-1, x.shape[-1])
+        n, dim = flat.shape[0], self.amp.shape[1]
+        if n <= chunk:
+            return self._eval(flat).reshape(x.shape[:-1] + (dim,))
+        from concurrent.futures import ThreadPoolExecutor
+        out = np.empty((n, dim))
+
+        def run(s):
+            out[s:s + chunk] = self._eval(flat[s:s + chunk])
+
+        with ThreadPoolExecutor(max(1, min(16, len(os.sched_getaffinity(0))))) as ex:
+            list(ex.map(run, range(0, n, chunk)))
+        return out.reshape(x.shape[:-1] + (dim,))
 
 
 def shear_wave(x, t, c, xi, eta, A=1.0):
