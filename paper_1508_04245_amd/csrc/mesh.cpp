@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <map>
 #include <unordered_map>
 
@@ -276,16 +277,59 @@ int build(int dim, int k, int64_t nvert, const double* xyz, int64_t nelem, const
   return 0;
 }
 
+// Processing order of the blocks of a 3D mesh: eight groups, by the band of the block's
+// centroid in y (eight bands), one group per XCD under the kernels' block remap (XCD x works
+// on the x-th eighth of the blocks); inside a group the blocks go by their lowest vertex z
+// (planes of elements), then in element order.  A group's plane is then small (a band of
+// y-rows), so the neighbours across the next plane are read within a few MiB of the XCD's
+// L2 traffic and are still there.  The results do not depend on this order (every element is
+// computed alone).  2D meshes, and DGCONV_BLOCK_ORDER=0, keep the element order.
+static std::vector<int64_t> block_order(const Host& H, int64_t bsz, int64_t nblk) {
+  std::vector<int64_t> ord(nblk);
+  for (int64_t b = 0; b < nblk; ++b) ord[b] = b;
+  const char* env = std::getenv("DGCONV_BLOCK_ORDER");
+  if (H.dim != 3 || nblk < 8 || (env && std::string(env) == "0")) return ord;
+  const int nv = 4;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (size_t i = 0; i < H.X.size(); ++i) {
+    lo[i % 3] = std::min(lo[i % 3], H.X[i]);
+    hi[i % 3] = std::max(hi[i % 3], H.X[i]);
+  }
+  std::vector<int> grp(nblk);
+  std::vector<double> zkey(nblk);
+  for (int64_t b = 0; b < nblk; ++b) {
+    const int64_t t0 = b * bsz, t1 = std::min<int64_t>(H.E, t0 + bsz);
+    double cy = 0, zmin = 1e300;
+    for (int64_t t = t0; t < t1; ++t)
+      for (int v = 0; v < nv; ++v) {
+        const double* x = &H.X[(t * nv + v) * 3];
+        cy += x[1];
+        zmin = std::min(zmin, x[2]);
+      }
+    cy /= (double)(t1 - t0) * nv;
+    grp[b] = std::min(7, std::max(0, (int)(8.0 * (cy - lo[1]) / (hi[1] - lo[1]))));
+    zkey[b] = zmin;
+  }
+  std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+    return grp[a] != grp[b] ? grp[a] < grp[b] : zkey[a] < zkey[b];
+  });
+  return ord;
+}
+
 // Tiles of `width` elements: the mesh is cut into blocks of 4*width consecutive elements (one
-// workgroup of 4 wavefronts each); inside a block the elements are grouped by class into
-// tiles, and the block's tile count is padded to a multiple of 4 with empty tiles (class -1),
-// so every tile of a workgroup covers the same contiguous range of the state arrays.
+// workgroup of 4 wavefronts each, taken in block_order); inside a block the elements are
+// grouped by class into tiles, and the block's tile count is padded to a multiple of 4 with
+// empty tiles (class -1), so every tile of a workgroup covers the same contiguous range of the
+// state arrays.
 void build_tiles(const Host& H, int width, std::vector<int32_t>& elem_list,
                  std::vector<int32_t>& tile_type, int& ntiles, bool by_class) {
   elem_list.clear();
   tile_type.clear();
   const int64_t bsz = 4 * width;
-  for (int64_t b0 = 0; b0 < H.E; b0 += bsz) {
+  const int64_t nblk = (H.E + bsz - 1) / bsz;
+  const std::vector<int64_t> ord = block_order(H, bsz, nblk);
+  for (int64_t bi = 0; bi < nblk; ++bi) {
+    const int64_t b0 = ord[bi] * bsz;
     const int64_t b1 = std::min<int64_t>(H.E, b0 + bsz);
     std::map<int, std::vector<int32_t>> by_type;
     for (int64_t t = b0; t < b1; ++t) by_type[by_class ? H.type_of[t] : 0].push_back((int32_t)t);
