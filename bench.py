@@ -76,10 +76,12 @@ CONFIGS = {
 
 
 def shape_counts(dim, k):
+    """Basis functions, volume points of the library's rule (the symmetric rule where it has
+    one), facet points."""
+    import paper_1508_04245_amd as dg
     np_ = (k + 1) * (k + 2) // 2 if dim == 2 else (k + 1) * (k + 2) * (k + 3) // 6
-    nv = max(1, (3 * k + 1) // 2)
     nf = max(1, (3 * k + 2) // 2)
-    nq = nv ** dim
+    nq = len(dg.volume_rule(dim, k)[1])
     nfq = nf ** (dim - 1)
     return np_, nq, nfq
 

@@ -67,7 +67,7 @@ typedef struct {
   int dim, k, n_basis;      /* n_basis = C(k+dim, dim) per component */
   int64_t n_elem, n_facet;  /* n_facet = (n_elem (dim+1) + n_bfacet) / 2 */
   int64_t n_dof;            /* n_elem * dim * n_basis */
-  int nq_vol, nq_facet;     /* quadrature points per element volume / per facet */
+  int nq_vol, nq_facet;     /* quadrature points per element volume (dg_volume_rule) / per facet */
   int n_types, n_tiles;     /* element classes with identical facet tables; 64-wide tiles */
   double h_min;             /* smallest facet measure (2D) or its square root (3D) */
   double volume;            /* sum of element volumes */
@@ -230,8 +230,8 @@ dg_status dg_transfer_transpose(const dg_mesh* mesh, const double* f, double* g_
 
 /* Reductions of FP64 states into out_dev (dev, doubles), deterministic (fixed summation
  * order, two passes over per-block partial results in a mesh-owned buffer):
- *   DG_RED_MAXVEL   out[0] = max over the volume quadrature points of |a(x)| (the speed in
- *                   the substep size)
+ *   DG_RED_MAXVEL   out[0] = max of |a(x)| over the points of the collapsed Gauss-Jacobi rule
+ *                   with ceil(3k/2)^dim points per element (the speed in the substep size)
  *   DG_RED_ENERGY   out[0] = 1/2 int |a|^2 dx, the kinetic energy whose stability the upwind
  *                   form gives (Sec. 2.3, eq. convstab; Sec. 2.5, the energy estimate of the
  *                   semidiscrete formulation)
@@ -338,6 +338,16 @@ dg_status dg_surrogate_warm_start(const dg_mesh* mesh, dg_surrogate* s, const do
  * if grads is not NULL, reference gradients [n_pts][n_basis][dim] at pts [n_pts][dim]. */
 dg_status dg_eval_basis(int dim, int k, int64_t n_pts, const double* pts, double* vals,
                         double* grads);
+
+/* The volume quadrature rule of the operator's volume term (Sec. 2.3, the cell integral of
+ * C^V; its integrand has degree 3k-1, and the rule is exact to that degree, so it does not
+ * change the operator): *n_out = number of points; if pts_out and wts_out are not NULL,
+ * host pts_out [n][dim] in reference coordinates (= barycentric coordinates 1..dim) and
+ * wts_out [n] summing to the reference simplex measure (1/2, 1/6).  A fully symmetric rule
+ * with positive weights and interior points where the library has one (2D k 1..4,
+ * 3D k 1..3), else the collapsed Gauss-Jacobi rule with ceil(3k/2)^dim points.  Host only.
+ * Errors: DG_EINVAL (dim, k out of range, n_out NULL). */
+dg_status dg_volume_rule(int dim, int k, int* n_out, double* pts_out, double* wts_out);
 
 const char* dg_last_error(void);
 const char* dg_version(void);

@@ -68,6 +68,7 @@ def lib():
         "dg_reduce": [P, I, P, P, P, P],
         "dg_reduce_noalloc": [P, I, P, P, P, P],
         "dg_eval_basis": [I, I, I64, P, P, P],
+        "dg_volume_rule": [I, I, P, P, P],
         "dg_surrogate_n_params": [P],
         "dg_surrogate_create": [P, I, P],
         "dg_surrogate_destroy": [P],
@@ -126,6 +127,17 @@ def eval_basis(dim, k, pts):
     grads = np.zeros((n, npb, dim))
     _check(lib().dg_eval_basis(dim, k, n, _ptr(pts), _ptr(vals), _ptr(grads)))
     return vals, grads
+
+
+def volume_rule(dim, k):
+    """The library's volume quadrature rule: points [n, dim] (reference coordinates) and
+    weights [n] (host)."""
+    n = ctypes.c_int(0)
+    _check(lib().dg_volume_rule(dim, k, ctypes.byref(n), None, None))
+    pts = np.zeros((n.value, dim))
+    wts = np.zeros(n.value)
+    _check(lib().dg_volume_rule(dim, k, ctypes.byref(n), _ptr(pts), _ptr(wts)))
+    return pts, wts
 
 
 class Mesh:

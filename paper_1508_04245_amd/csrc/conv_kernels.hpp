@@ -29,13 +29,18 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "volume_rules.hpp"
+
 namespace dgk {
 
 template <int D, int K>
 struct Shape {
   static constexpr int NP = D == 2 ? (K + 1) * (K + 2) / 2 : (K + 1) * (K + 2) * (K + 3) / 6;
-  static constexpr int NV1 = (3 * K + 1) / 2 < 1 ? 1 : (3 * K + 1) / 2;  // exact to 3k-1
-  static constexpr int NQ = D == 2 ? NV1 * NV1 : NV1 * NV1 * NV1;
+  // collapsed rule exact to 3k-1: NV1 points per direction, NS in all (the points of the
+  // speed reduction); the volume rule is the symmetric one with fewer points where it exists
+  static constexpr int NV1 = (3 * K + 1) / 2 < 1 ? 1 : (3 * K + 1) / 2;
+  static constexpr int NS = D == 2 ? NV1 * NV1 : NV1 * NV1 * NV1;
+  static constexpr int NQ = dgref::sym_vol_points(D, K) > 0 ? dgref::sym_vol_points(D, K) : NS;
   static constexpr int NF1 = (3 * K + 2) / 2 < 1 ? 1 : (3 * K + 2) / 2;  // exact to 3k
   static constexpr int NFQ = D == 2 ? NF1 : NF1 * NF1;
   static constexpr int NPERM = D == 2 ? 2 : 6;

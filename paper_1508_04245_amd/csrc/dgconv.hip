@@ -84,10 +84,11 @@ elem_reduce_kernel(int what, int dim, int np, int64_t E, const double* __restric
     for (int c = 0; c < 3; ++c) partial[blockIdx.x * 3 + c] = sh[0][c];
 }
 
-// max over the volume points of |w|, per block
+// max over the points of the collapsed rule exact to 3k-1 of |w|, per block (spd: the basis
+// values there, [NS][NP])
 template <int D, int K>
 __global__ void __launch_bounds__(kRedBlock)
-maxvel_kernel(int64_t E, const double* __restrict__ a, const double* __restrict__ tab,
+maxvel_kernel(int64_t E, const double* __restrict__ a, const double* __restrict__ spd,
               double* __restrict__ partial) {
   using S = dgk::Shape<D, K>;
   __shared__ double sh[kRedBlock];
@@ -95,11 +96,11 @@ maxvel_kernel(int64_t E, const double* __restrict__ a, const double* __restrict_
   double mx = 0;
   if (t < E) {
     const double* pa = a + t * D * S::NP;
-    for (int q = 0; q < S::NQ; ++q) {
+    for (int q = 0; q < S::NS; ++q) {
       double s = 0;
       for (int i = 0; i < D; ++i) {
         double w = 0;
-        for (int m = 0; m < S::NP; ++m) w = fma(tab[S::OFF_BV + q * S::NP + m], pa[i * S::NP + m], w);
+        for (int m = 0; m < S::NP; ++m) w = fma(spd[q * S::NP + m], pa[i * S::NP + m], w);
         s = fma(w, w, s);
       }
       mx = fmax(mx, s);
@@ -143,9 +144,11 @@ final_reduce_kernel(int nblocks, int is_max, int nout, int sqrt_out,
 // ------------------------------------------------------------------ dispatch
 template <int D, int K>
 hipError_t launch_maxvel(const dg_mesh* m, const double* a, double* partial, hipStream_t s) {
+  if (dgk::Shape<D, K>::NS != m->t.ns || dgk::Shape<D, K>::NP != m->h.np)
+    return hipErrorInvalidValue;
   const int nb = (int)((m->h.E + kRedBlock - 1) / kRedBlock);
   hipLaunchKernelGGL((maxvel_kernel<D, K>), dim3(nb), dim3(kRedBlock), 0, s, m->h.E, a,
-                     m->d_tab, partial);
+                     m->d_spd, partial);
   return hipGetLastError();
 }
 
@@ -694,6 +697,7 @@ dg_status dgi::ensure_device(const dg_mesh* cm) {
   std::vector<double> zeros((size_t)m->n_partial * 3, 0.0);
   dg_status s = DG_OK;
   if ((s = upload(m->t.data, &m->d_tab)) != DG_OK || (s = upload(tabf, &m->d_tab_f)) != DG_OK ||
+      (s = upload(m->t.spd, &m->d_spd)) != DG_OK ||
       (s = upload(m->h.jinv, &m->d_jinv)) != DG_OK || (s = upload(jinvf, &m->d_jinv_f)) != DG_OK ||
       (s = upload(m->h.absdet, &m->d_absdet)) != DG_OK ||
       (s = upload(m->h.nbr, &m->d_nbr)) != DG_OK ||
@@ -722,7 +726,7 @@ using dgi::ensure_device;
 
 void free_mesh(dg_mesh* m) {
   if (!m) return;
-  void* ptrs[] = {m->d_tab, m->d_tab_f, m->d_jinv, m->d_jinv_f, m->d_absdet, m->d_nbr,
+  void* ptrs[] = {m->d_tab, m->d_spd, m->d_tab_f, m->d_jinv, m->d_jinv_f, m->d_absdet, m->d_nbr,
                   m->d_elem_list, m->d_tile_type, m->d_type_tab, m->d_elem_tab, m->d_work,
                   m->d_partial, m->d_rich_partial, m->d_rich_state, m->d_elem_list16,
                   m->d_tile_type16, m->d_frag[0], m->d_frag[1], m->d_frag[2], m->d_hfacet,
@@ -871,6 +875,20 @@ void dg_mesh_destroy(dg_mesh* mesh) {
   if (!mesh) return;
   if (mesh->on_device) (void)hipDeviceSynchronize();
   free_mesh(mesh);
+}
+
+dg_status dg_volume_rule(int dim, int k, int* n_out, double* pts_out, double* wts_out) {
+  dg_status st = check_k(dim, k);
+  if (st != DG_OK) return st;
+  if (!n_out) return fail(DG_EINVAL, "null pointer");
+  std::vector<double> p, w;
+  dgref::volume_rule<double>(dim, k, p, w);
+  *n_out = (int)w.size();
+  if (pts_out && wts_out) {
+    std::memcpy(pts_out, p.data(), p.size() * sizeof(double));
+    std::memcpy(wts_out, w.data(), w.size() * sizeof(double));
+  }
+  return DG_OK;
 }
 
 dg_status dg_eval_basis(int dim, int k, int64_t n_pts, const double* pts, double* vals,

@@ -30,6 +30,7 @@ struct dg_mesh {
   dgmesh::Tables t;
   int device = 0;
   double* d_tab = nullptr;
+  double* d_spd = nullptr;   // basis values at the speed-reduction points
   float* d_tab_f = nullptr;
   double* d_jinv = nullptr;
   float* d_jinv_f = nullptr;

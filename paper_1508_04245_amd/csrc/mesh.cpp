@@ -424,7 +424,7 @@ void build_tables(int dim, int k, Tables& T) {
   using dgref::real;
   const int d = dim, np = dgref::n_basis(d, k);
   std::vector<real> vp, vw, fp, fw;
-  dgref::collapsed_rule<real>(d, dgref::vol_points_1d(k), vp, vw);
+  dgref::volume_rule<real>(d, k, vp, vw);
   dgref::facet_rule<real>(d, dgref::facet_points_1d(k), fp, fw);
   T.nq = (int)vw.size();
   T.nfq = (int)fw.size();
@@ -443,6 +443,16 @@ void build_tables(int dim, int k, Tables& T) {
       T.data[T.off_bv + q * np + m] = (double)val[m];
       for (int j = 0; j < d; ++j)
         T.data[T.off_dv + (q * np + m) * d + j] = (double)(vw[q] * grad[m * d + j]);
+    }
+  }
+  {
+    std::vector<real> sp, sw;
+    dgref::collapsed_rule<real>(d, dgref::vol_points_1d(k), sp, sw);
+    T.ns = (int)sw.size();
+    T.spd.assign((size_t)T.ns * np, 0.0);
+    for (int q = 0; q < T.ns; ++q) {
+      dgref::eval_basis_t<real>(d, k, &sp[q * d], val.data(), nullptr);
+      for (int m = 0; m < np; ++m) T.spd[(size_t)q * np + m] = (double)val[m];
     }
   }
   const real vref[4][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};

@@ -61,10 +61,12 @@ void boundary_points(const Host& H, std::vector<double>& out);
 //   Tr [(d+1)*P][nfq][np]  phi_m at the canonical facet points of local facet f with
 //                          canonical permutation p (table index f*P + p, P = d!)
 //   Lf [(d+1)*P][nfq][np]  facet weight times Tr
+// and, apart, the basis values at the ns points of the collapsed rule exact to 3k-1 (the
+// points of the speed reduction, independent of the volume rule): spd [ns][np].
 struct Tables {
-  int nq = 0, nfq = 0, nperm = 0;
+  int nq = 0, nfq = 0, nperm = 0, ns = 0;
   size_t off_bv = 0, off_dv = 0, off_tr = 0, off_lf = 0, total = 0;
-  std::vector<double> data;
+  std::vector<double> data, spd;
 };
 void build_tables(int dim, int k, Tables& t);
 

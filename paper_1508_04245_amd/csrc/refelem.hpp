@@ -15,12 +15,14 @@
 // degree ascending, then r descending, then q descending.
 //
 // Quadrature: Gauss-Jacobi nodes by Newton iteration with polynomial deflation; collapsed
-// (Duffy) tensor rules on the simplex.  Everything is evaluated in long double and rounded to
+// (Duffy) tensor rules on the simplex; the fully symmetric volume rules of volume_rules.hpp
+// (fewer points at the same degree) where there is one.  Everything is evaluated in long double and rounded to
 // FP64 once, so the device tables are correctly rounded up to a few ulp.
 #pragma once
 #include <array>
 #include <cmath>
 #include <vector>
+#include "volume_rules.hpp"
 
 namespace dgref {
 
@@ -228,6 +230,21 @@ inline void facet_rule(int dim, int n, std::vector<T>& pts, std::vector<T>& wts)
 }
 
 inline int vol_points_1d(int k) { int n = (3 * k + 1) / 2; return n < 1 ? 1 : n; }   // exact to 3k-1
+
+// The volume rule of the operator, exact to degree 3k-1 (the degree of the volume integrand):
+// the fully symmetric rule of volume_rules.hpp where there is one, else the collapsed rule
+// with vol_points_1d(k) points per direction.  Weights sum to |T^|.
+template <typename T>
+inline void volume_rule(int dim, int k, std::vector<T>& pts, std::vector<T>& wts) {
+  const long double *p = nullptr, *w = nullptr;
+  if (sym_vol_rule(dim, k, &p, &w)) {
+    const int n = sym_vol_points(dim, k);
+    pts.assign(p, p + (size_t)n * dim);
+    wts.assign(w, w + n);
+    return;
+  }
+  collapsed_rule<T>(dim, vol_points_1d(k), pts, wts);
+}
 inline int facet_points_1d(int k) { int n = (3 * k + 2) / 2; return n < 1 ? 1 : n; } // exact to 3k
 
 }  // namespace dgref

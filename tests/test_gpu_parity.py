@@ -170,7 +170,7 @@ def test_reductions(dg):
     l2 = m.reduce("l2diff", ad, bd).cpu().numpy()[:2]
     assert abs(l2[0] / l2[1] - sp.rel_l2(a, b)) <= 1e-12
     mv = m.reduce("maxvel", ad).cpu().numpy()[0]
-    # the library's volume rule differs from the oracle's: compare on the library's points
+    # the speed reduction is defined on the collapsed rule with ceil(3k/2) points per direction
     assert abs(mv - sp.max_speed(a, n=(3 * k + 1) // 2)) <= 1e-13 * mv
     bad = a.copy()
     bad[3, 1, 2] = np.nan

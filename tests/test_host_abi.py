@@ -290,3 +290,42 @@ def test_reduce_noalloc_errors_before_device_work():
     assert L.dg_reduce_noalloc(m._h, 3, a, None, out, None) == -1  # L2DIFF without b
     assert L.dg_reduce_noalloc(m._h, 9, a, None, out, None) == -1  # unknown reduction
     assert L.dg_reduce_noalloc(m._h, 1, None, None, out, None) == -1
+
+
+def _simplex_moment(e):
+    """int over the reference simplex of prod x_a^e_a = prod e_a! / (sum e + dim)!"""
+    from math import factorial
+    num = 1
+    for a in e:
+        num *= factorial(a)
+    return num / factorial(sum(e) + len(e))
+
+
+@pytest.mark.parametrize("dim,k", [(2, k) for k in range(7)] + [(3, k) for k in range(5)])
+def test_volume_rule_exact_to_the_volume_integrand_degree(dim, k):
+    """The library's volume rule integrates every monomial of degree <= 3k-1 (the degree of the
+    volume integrand (u (x) w) : grad phi) exactly, against the closed form; positive weights,
+    points inside the simplex; the symmetric rules are invariant under every permutation of
+    the vertices and need fewer points than the collapsed rule of ceil(3k/2) per direction."""
+    pts, wts = dg.volume_rule(dim, k)
+    deg = max(0, 3 * k - 1)
+    n_coll = max(1, (3 * k + 1) // 2) ** dim
+    assert pts.shape == (len(wts), dim) and len(wts) <= n_coll
+    for e in itertools.product(range(deg + 1), repeat=dim):
+        if sum(e) > deg:
+            continue
+        got = float(np.sum(wts * np.prod(pts ** np.array(e), axis=1)))
+        ex = _simplex_moment(e)
+        assert abs(got - ex) <= 2e-15 * ex * max(1, len(wts)) ** 0.5, (e, got, ex)
+    bary = np.concatenate([1 - pts.sum(1, keepdims=True), pts], 1)
+    assert np.all(wts > 0) and bary.min() > 0
+    symmetric = (dim, k) in [(2, 1), (2, 2), (2, 3), (2, 4), (3, 1), (3, 2), (3, 3)]
+    if symmetric:
+        assert len(wts) < n_coll
+        key = {tuple(np.round(b, 12)): w for b, w in zip(bary, wts)}
+        for perm in itertools.permutations(range(dim + 1)):
+            for b, w in zip(bary, wts):
+                pb = tuple(np.round(b[list(perm)], 12))
+                assert pb in key and abs(key[pb] - w) <= 1e-15, (perm, b)
+    m = dg.Mesh.box(dim, 2 if dim == 3 else 3, k)
+    assert m.info["nq_vol"] == len(wts)
