@@ -238,15 +238,19 @@ hipError_t gemm(const GemmArgs& g, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ fused inference
-// The whole network for a block of kRB rows in one workgroup (inference: no pre-activations
-// are kept).  The inputs and each layer's activations stay in LDS as BF16; the weights are
-// read from L2 (the BF16 copy, every block reads each layer once).  Layers 1-3: wave w
-// computes columns [64 w, 64 w + 64) of all kRB rows as 4 x 4 tiles of v_mfma_f32_16x16x32_bf16
-// (K = 32 per instruction, the operands' 8 K values of lane l at 8 (l / 16)); the activation
+// The whole network for a block of kRB rows in one workgroup of 4 waves (inference: no
+// pre-activations are kept).  The inputs and each layer's activations stay in LDS as BF16,
+// row-major; the weights are read from L2 (the BF16 copy, every block reads each layer once).
+// Each layer is computed transposed, out^T = W h^T, with v_mfma_f32_16x16x32_bf16 (K = 32 per
+// instruction): the weight rows are the A operand (lane l: row l % 16, its 8 K values at
+// 8 (l / 16)), the activation rows the B operand, so a lane's four results are four
+// consecutive features of one row, stored to LDS as one 8-byte write of packed BF16.  Layers
+// 1-3: wave w computes features [64 w, + 64) of the kRB rows as 4 x 4 tiles; the activation
 // overwrites the layer's input in place once every wave has finished reading it.  Layer 4:
-// wave w computes rows [16 w, 16 w + 16) of the 20 outputs (two 16-column tiles).  LDS rows
-// are padded by 8 elements so that the 16-byte operand reads of a tile's 16 rows spread over
-// the banks.
+// wave w computes rows [16 w, + 16) of the 20 outputs (two 16-feature tiles).  LDS rows are
+// padded by 8 elements so the 16-byte operand reads of a tile's 16 rows spread over the
+// banks.  Two or three workgroups share a compute unit (47 KiB of LDS each), so one's GELU
+// phase overlaps another's matrix phase.
 constexpr int kRB = 64;                    // rows per workgroup
 constexpr int kXLD = 96 + 8, kHLD = kHid + 8;
 
@@ -255,6 +259,62 @@ constexpr int kXLD = 96 + 8, kHLD = kHid + 8;
 __device__ __forceinline__ s8 wload8(const uint16_t* W, int fin, int n, int k) {
   if (k >= fin) return s8{0, 0, 0, 0, 0, 0, 0, 0};
   return __builtin_bit_cast(s8, *(const uint4*)(W + (int64_t)n * fin + k));
+}
+
+// GELU of the inference kernel: erf by Abramowitz and Stegun, Handbook of Mathematical
+// Functions, 7.1.26 (erf x = 1 - (a1 t + .. + a5 t^5) e^(-x^2), t = 1 / (1 + p x), x >= 0,
+// absolute error <= 1.5e-7, far below the BF16 rounding of the activations), in the
+// branch-free form gelu(z) = max(z, 0) - |z| / 2 (1 - erf(|z| / sqrt 2)), with the hardware
+// reciprocal and base-2 exponential
+__device__ __forceinline__ float gelu_fast(float z) {
+  const float a = fabsf(z), s = a * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, s, 1.0f));
+  float q = fmaf(1.061405429f, t, -1.453152027f);
+  q = fmaf(q, t, 1.421413741f);
+  q = fmaf(q, t, -0.284496736f);
+  q = fmaf(q, t, 0.254829592f);
+  const float e = (q * t) * __builtin_amdgcn_exp2f(-1.4426950408889634f * s * s);
+  return fmaf(-0.5f * a, e, fmaxf(z, 0.0f));
+}
+
+// one hidden layer for the wave's 64 features x 64 rows: src [kRB][ld] -> sh (in place when
+// src == sh), FIN input features (a multiple of 32 after zero padding of the weights' K)
+template <int FIN, int FINW>
+__device__ __forceinline__ void mlp_hidden(const uint16_t* src, int ld, uint16_t* sh,
+                                           const uint16_t* __restrict__ W,
+                                           const float* __restrict__ bias, int f0, int rw0,
+                                           int g, int c) {
+  // the accumulators start at the bias of their four features
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float4 bn = *(const float4*)(bias + f0 + 16 * i + 4 * g);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{bn.x, bn.y, bn.z, bn.w};
+  }
+#pragma unroll
+  for (int k0 = 0; k0 < FIN; k0 += 32) {
+    s8 a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = wload8(W, FINW, f0 + 16 * i + c, k0 + 8 * g);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = *(const s8*)(&src[(rw0 + 16 * j + c) * ld + k0 + 8 * g]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = mfma32(a[i], b[j], acc[i][j]);
+  }
+  __syncthreads();  // every wave has read the layer's input
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+      const bf4 v = {(__bf16)gelu_fast(acc[i][j][0]), (__bf16)gelu_fast(acc[i][j][1]),
+                     (__bf16)gelu_fast(acc[i][j][2]), (__bf16)gelu_fast(acc[i][j][3])};
+      *(bf4*)(&sh[(rw0 + 16 * j + c) * kHLD + f0 + 16 * i + 4 * g]) = v;
+    }
+  __syncthreads();
 }
 
 __global__ void __launch_bounds__(256) mlp_fused_kernel(int64_t B, const uint16_t* __restrict__ xb,
@@ -274,62 +334,36 @@ __global__ void __launch_bounds__(256) mlp_fused_kernel(int64_t B, const uint16_
     *(uint4*)(&sx[row * kXLD + 8 * ch]) = v;
   }
   __syncthreads();
-  const int n0 = 64 * w;
-  for (int l = 0; l < 3; ++l) {
-    const int fin = kFanIn[l];
-    const uint16_t* W = wbf + kOffW[l];
-    const float* bias = master + kOffW[l] + (int64_t)kHid * fin;
-    const uint16_t* src = l == 0 ? sx : sh;
-    const int ld = l == 0 ? kXLD : kHLD;
-    f4 acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = f4{0, 0, 0, 0};
-    for (int k0 = 0; k0 < fin; k0 += 32) {
-      s8 a[4], b[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = wload8(W, fin, n0 + 16 * j + c, k0 + 8 * g);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = *(const s8*)(&src[(16 * i + c) * ld + k0 + 8 * g]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = mfma32(a[i], b[j], acc[i][j]);
-    }
-    __syncthreads();  // every wave has read the layer's input
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = n0 + 16 * j + c;
-      const float bn = bias[n];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sh[(16 * i + 4 * g + r) * kHLD + n] = f2bf(gelu(acc[i][j][r] + bn));
-    }
-    __syncthreads();
-  }
-  // output layer: rows [16 w, 16 w + 16), columns 0 .. 19 of two 16-column tiles
+  const int f0 = 64 * w, rw0 = 0;
+  mlp_hidden<96, kIn>(sx, kXLD, sh, wbf + kOffW[0], master + kOffW[0] + (int64_t)kHid * kIn, f0,
+                      rw0, g, c);
+  mlp_hidden<kHid, kHid>(sh, kHLD, sh, wbf + kOffW[1], master + kOffW[1] + (int64_t)kHid * kHid,
+                         f0, rw0, g, c);
+  mlp_hidden<kHid, kHid>(sh, kHLD, sh, wbf + kOffW[2], master + kOffW[2] + (int64_t)kHid * kHid,
+                         f0, rw0, g, c);
+  // output layer: rows [16 w, 16 w + 16), features 0 .. 19 of two 16-feature tiles
   const uint16_t* W = wbf + kOffW[3];
   const float* bias = master + kOffW[3] + (int64_t)kOut * kHid;
   f4 acc[2] = {f4{0, 0, 0, 0}, f4{0, 0, 0, 0}};
-  for (int k0 = 0; k0 < kHid; k0 += 32) {
-    const s8 a = *(const s8*)(&sh[(16 * w + c) * kHLD + k0 + 8 * g]);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int n = 16 * j + c;
-      const s8 b = n < kOut ? wload8(W, kHid, n, k0 + 8 * g) : s8{0, 0, 0, 0, 0, 0, 0, 0};
-      acc[j] = mfma32(a, b, acc[j]);
+  for (int k0 = 0; k0 < kHid; k0 += 32) {
+    const s8 b = *(const s8*)(&sh[(16 * w + c) * kHLD + k0 + 8 * g]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int n = 16 * i + c;
+      const s8 a = n < kOut ? wload8(W, kHid, n, k0 + 8 * g) : s8{0, 0, 0, 0, 0, 0, 0, 0};
+      acc[i] = mfma32(a, b, acc[i]);
     }
   }
+  const int64_t row = r0 + 16 * w + c;
+  if (row < B) {
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int n = 16 * j + c;
-    if (n >= kOut) continue;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = r0 + 16 * w + 4 * g + r;
-      if (row < B) y[row * kOut + n] = acc[j][r] + bias[n];
+    for (int i = 0; i < 2; ++i) {
+      const int n = 16 * i + 4 * g;  // four consecutive outputs; 20 = 16 + 4
+      if (n >= kOut) continue;
+      const float4 bn = *(const float4*)(bias + n);
+      *(float4*)(y + row * kOut + n) =
+          make_float4(acc[i][0] + bn.x, acc[i][1] + bn.y, acc[i][2] + bn.z, acc[i][3] + bn.w);
     }
   }
 }

@@ -72,7 +72,8 @@ def test_forward_and_gradient_vs_oracle(env):
     say("   forward rel %.3e" % e)
     assert e < 3e-2
     # the fused inference kernel against the layer-by-layer training forward (the same BF16
-    # activations; the two differ only in the order of the FP32 accumulation)
+    # activations; the two differ in the order of the FP32 accumulation and in the inference
+    # GELU's erf, within 1.5e-7 of the exact one)
     loss, g = sur.grad(xd, td)
     l_fused = float(np.mean((y.astype(np.float64) - t) ** 2))
     say("   fused-forward loss %.6f, training-forward loss %.6f" % (l_fused, loss.item()))
