@@ -39,7 +39,7 @@ PEAK_HBM = 8.0e12
 TRAFFIC_SOURCES = ("paper_1508_04245_amd/csrc/conv_kernels.hpp",
                    "paper_1508_04245_amd/csrc/mfma_kernels.hpp",
                    "paper_1508_04245_amd/csrc/dgconv.hip",
-                   "paper_1508_04245_amd/csrc/volume_rules.hpp")
+                   "paper_1508_04245_amd/csrc/sym_rules.hpp")
 MEASURED_TRAFFIC = {
     ("c2", "fp64", "valu"): (88.5e6, "1216e7900dd90925"),
 }
@@ -77,13 +77,11 @@ CONFIGS = {
 
 
 def shape_counts(dim, k):
-    """Basis functions, volume points of the library's rule (the symmetric rule where it has
-    one), facet points."""
+    """Basis functions, volume points and facet points of the library's rules."""
     import paper_1508_04245_amd as dg
     np_ = (k + 1) * (k + 2) // 2 if dim == 2 else (k + 1) * (k + 2) * (k + 3) // 6
-    nf = max(1, (3 * k + 2) // 2)
     nq = len(dg.volume_rule(dim, k)[1])
-    nfq = nf ** (dim - 1)
+    nfq = len(dg.facet_rule(dim, k)[1])
     return np_, nq, nfq
 
 

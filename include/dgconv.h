@@ -67,7 +67,8 @@ typedef struct {
   int dim, k, n_basis;      /* n_basis = C(k+dim, dim) per component */
   int64_t n_elem, n_facet;  /* n_facet = (n_elem (dim+1) + n_bfacet) / 2 */
   int64_t n_dof;            /* n_elem * dim * n_basis */
-  int nq_vol, nq_facet;     /* quadrature points per element volume (dg_volume_rule) / per facet */
+  int nq_vol, nq_facet;     /* quadrature points per element volume / per facet (dg_volume_rule,
+                               dg_facet_rule) */
   int n_types, n_tiles;     /* element classes with identical facet tables; 64-wide tiles */
   double h_min;             /* smallest facet measure (2D) or its square root (3D) */
   double volume;            /* sum of element volumes */
@@ -348,6 +349,16 @@ dg_status dg_eval_basis(int dim, int k, int64_t n_pts, const double* pts, double
  * 3D k 1..3), else the collapsed Gauss-Jacobi rule with ceil(3k/2)^dim points.  Host only.
  * Errors: DG_EINVAL (dim, k out of range, n_out NULL). */
 dg_status dg_volume_rule(int dim, int k, int* n_out, double* pts_out, double* wts_out);
+
+/* The facet quadrature rule of the operator's facet terms (Sec. 2.3, the facet integrals of
+ * C^V with the upwind value taken pointwise, so the rule is part of the operator's
+ * definition): exact to degree 3k; *n_out = number of points; if pts_out and wts_out are not
+ * NULL, host pts_out [n][dim-1] (2D: s on the edge; 3D: (s, t), the point A + s (B - A) +
+ * t (C - A) of the facet's canonically ordered vertices) and wts_out [n] summing to 1.  2D:
+ * ceil((3k+1)/2) Gauss-Legendre points; 3D: the fully symmetric rule of degree 3k for k = 2
+ * (12 points) and k = 3 (19 points), else the collapsed rule with ceil((3k+1)/2)^2 points.
+ * Host only.  Errors: DG_EINVAL (dim, k out of range, n_out NULL). */
+dg_status dg_facet_rule(int dim, int k, int* n_out, double* pts_out, double* wts_out);
 
 const char* dg_last_error(void);
 const char* dg_version(void);

@@ -22,7 +22,9 @@ Readings where the paper leaves the hot path open:
   * "Self" mode u := w gives the nonlinear div(w (x) w); a caller-given u gives the linear
     operator C^V(u) of the propagation problem with frozen convection.
   * The upwind value is taken pointwise at the facet quadrature points, so the facet rule
-    (refelem.facet_rule, canonical orientation from mesh.Mesh) is part of the definition.
+    (refelem.operator_facet_rule, canonical orientation from mesh.Mesh) is part of the
+    definition: Gauss-Legendre points on an edge; on a triangle, the symmetric rule of degree
+    3k (k = 2, 3: 12 and 19 points) where it needs fewer points than the collapsed rule.
   * Time integrator: three-stage SSP-RK3 (Shu-Osher form); the paper leaves the explicit
     integrator of the propagation problem generic.
 """
@@ -42,7 +44,7 @@ class Space:
         self.vq, self.vw = R.collapsed_rule(d, R.volume_points_for_oracle(k))
         self.phi_v = R.eval_basis(d, k, self.vq)  # [Q, Np]
         self.dphi_v = R.eval_grad(d, k, self.vq)  # [Q, Np, d]
-        self.fq, self.fw = R.facet_rule(d, R.facet_points(k))  # [Qf, d-1], weights sum to 1
+        self.fq, self.fw = R.operator_facet_rule(d, k)  # [Qf, d-1], weights sum to 1
         self.chunk = chunk
         # the diagonal of M^V: int_T phi_m phi_m dx, by quadrature on every element
         self.mass = mesh.absdetJ[:, None] * np.einsum("q,qm,qm->m", self.vw, self.phi_v,

@@ -24,6 +24,7 @@ formula to get wrong); pinned against central differences.
 Quadrature.  Collapsed (Duffy) tensor rules: n Gauss-Legendre points in a, n Gauss-Jacobi
 (alpha=1) in b, n Gauss-Jacobi (alpha=2) in c; exact for total degree <= 2n-1.
 """
+import functools
 from math import comb
 
 import numpy as np
@@ -155,6 +156,97 @@ def facet_rule(dim, n):
         return ((1 + x) / 2.0)[:, None], w / 2.0
     p, w = collapsed_rule(2, n)
     return p, w * 2.0
+
+
+# Fully symmetric triangle rules with positive weights and interior points: the degree-6
+# rule with 12 points and the degree-9 rule with 19 points of D. A. Dunavant, "High degree
+# efficient symmetrical Gaussian quadrature rules for the triangle", Int. J. Numer. Methods
+# Eng. 21 (1985) 1129-1148.  Each is given by its orbits under the vertex permutations, with
+# barycentric generators ("3": the centroid; "21": (a, a, 1-2a); "111": (a, b, 1-a-b)), and
+# starting values of the free parameters to three digits; Gauss-Newton on the moment
+# equations fixes them and the weights.  The equations integrate the orthonormal basis of
+# degree <= the rule's degree (int phi_m = |T^|^(1/2) delta_m0), which keeps them well
+# conditioned; the pins check the result against the exact monomial integrals.
+_SYM_TRI = {
+    6: [("21", (0.063,)), ("21", (0.249,)), ("111", (0.053, 0.310))],
+    9: [("3", ()), ("21", (0.045,)), ("21", (0.188,)), ("21", (0.437,)), ("21", (0.490,)),
+        ("111", (0.037, 0.222))],
+}
+
+
+def _tri_orbit(kind, p):
+    """Distinct permutations of a barycentric generator, as (s, t) = (l1, l2) rows."""
+    import itertools
+    if kind == "3":
+        g = (1.0 / 3, 1.0 / 3, 1.0 / 3)
+    elif kind == "21":
+        g = (p[0], p[0], 1.0 - 2.0 * p[0])
+    else:
+        g = (p[0], p[1], 1.0 - p[0] - p[1])
+    out = []
+    for perm in itertools.permutations(range(3)):
+        b = tuple(g[i] for i in perm)
+        if not any(np.allclose(b, c, rtol=0, atol=1e-12) for c in out):
+            out.append(b)
+    return np.array(out)[:, 1:]
+
+
+@functools.lru_cache(maxsize=None)
+def symmetric_triangle_rule(degree):
+    """The symmetric rule of _SYM_TRI for `degree` on the unit triangle: points (s, t) [Q, 2],
+    weights summing to 1/2 (the area)."""
+    spec = _SYM_TRI[degree]
+    target = np.zeros(n_basis(2, degree))
+    target[0] = np.sqrt(0.5)
+    npar = [len(p) for _, p in spec]
+    npos = sum(npar)
+
+    def moments_matrix(x):
+        cols, k = [], 0
+        for (kind, _), n in zip(spec, npar):
+            P = _tri_orbit(kind, x[k:k + n])
+            k += n
+            cols.append(eval_basis(2, degree, P).sum(axis=0))
+        return np.stack(cols, axis=1)
+
+    def resid(z):
+        return moments_matrix(z[:npos]) @ z[npos:] - target
+
+    pos = np.array([v for _, p in spec for v in p], dtype=np.float64)
+    w = np.linalg.lstsq(moments_matrix(pos), target, rcond=None)[0]
+    z = np.concatenate([pos, w])
+    for it in range(12):
+        r = resid(z)
+        J = np.empty((len(r), len(z)))
+        for c in range(len(z)):
+            hz = 1e-7
+            zp, zm = z.copy(), z.copy()
+            zp[c] += hz
+            zm[c] -= hz
+            J[:, c] = (resid(zp) - resid(zm)) / (2 * hz)
+        dz = np.linalg.lstsq(J, r, rcond=None)[0]
+        z = z - dz
+        if np.abs(dz).max() < 1e-15:  # quadratic convergence: the next step is at rounding
+            break
+    pos, w = z[:npos], z[npos:]
+    assert np.abs(resid(z)).max() < 1e-15 and np.all(w > 0)
+    pts, wts, k = [], [], 0
+    for (kind, _), n, wo in zip(spec, npar, w):
+        P = _tri_orbit(kind, pos[k:k + n])
+        k += n
+        pts.append(P)
+        wts.append(np.full(len(P), wo))
+    return np.concatenate(pts), np.concatenate(wts)
+
+
+def operator_facet_rule(dim, k):
+    """The facet rule of the convection operator: exact to degree 3k, weights summing to 1.
+    2D: facet_rule(2, facet_points(k)).  3D: the symmetric rule of degree 3k where there is
+    one (k = 2: 12 points, k = 3: 19 points), else facet_rule(3, facet_points(k))."""
+    if dim == 3 and 3 * k in _SYM_TRI:
+        p, w = symmetric_triangle_rule(3 * k)
+        return p, 2.0 * w
+    return facet_rule(dim, facet_points(k))
 
 
 def volume_points_for_oracle(k):

@@ -69,6 +69,7 @@ def lib():
         "dg_reduce_noalloc": [P, I, P, P, P, P],
         "dg_eval_basis": [I, I, I64, P, P, P],
         "dg_volume_rule": [I, I, P, P, P],
+        "dg_facet_rule": [I, I, P, P, P],
         "dg_surrogate_n_params": [P],
         "dg_surrogate_create": [P, I, P],
         "dg_surrogate_destroy": [P],
@@ -137,6 +138,17 @@ def volume_rule(dim, k):
     pts = np.zeros((n.value, dim))
     wts = np.zeros(n.value)
     _check(lib().dg_volume_rule(dim, k, ctypes.byref(n), _ptr(pts), _ptr(wts)))
+    return pts, wts
+
+
+def facet_rule(dim, k):
+    """The library's facet quadrature rule of the operator: points [n, dim - 1] (facet
+    parameters) and weights [n] summing to 1 (host)."""
+    n = ctypes.c_int(0)
+    _check(lib().dg_facet_rule(dim, k, ctypes.byref(n), None, None))
+    pts = np.zeros((n.value, dim - 1))
+    wts = np.zeros(n.value)
+    _check(lib().dg_facet_rule(dim, k, ctypes.byref(n), _ptr(pts), _ptr(wts)))
     return pts, wts
 
 

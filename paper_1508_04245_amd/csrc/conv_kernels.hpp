@@ -29,7 +29,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
-#include "volume_rules.hpp"
+#include "sym_rules.hpp"
 
 namespace dgk {
 
@@ -41,8 +41,12 @@ struct Shape {
   static constexpr int NV1 = (3 * K + 1) / 2 < 1 ? 1 : (3 * K + 1) / 2;
   static constexpr int NS = D == 2 ? NV1 * NV1 : NV1 * NV1 * NV1;
   static constexpr int NQ = dgref::sym_vol_points(D, K) > 0 ? dgref::sym_vol_points(D, K) : NS;
-  static constexpr int NF1 = (3 * K + 2) / 2 < 1 ? 1 : (3 * K + 2) / 2;  // exact to 3k
-  static constexpr int NFQ = D == 2 ? NF1 : NF1 * NF1;
+  // facet rule exact to 3k: NF1 Gauss points on an edge; on a triangle the symmetric rule
+  // where there is one, else NF1^2 collapsed points
+  static constexpr int NF1 = (3 * K + 2) / 2 < 1 ? 1 : (3 * K + 2) / 2;
+  static constexpr int NFQ = D == 2 ? NF1
+                                    : (dgref::sym_facet_points(K) > 0 ? dgref::sym_facet_points(K)
+                                                                      : NF1 * NF1);
   static constexpr int NPERM = D == 2 ? 2 : 6;
   static constexpr int NTAB = (D + 1) * NPERM;
   static constexpr int OFF_BV = 0;
@@ -183,7 +187,7 @@ constexpr int min_waves() { return Shape<D, K>::NP * D * sizeof(T) <= 15 * 2 * 8
 // leave class-grouped tiles mostly empty.  Boundary facets are then selected per lane.
 template <int D, int K, typename T>
 constexpr bool lane_tables_ok() {
-  return (size_t)(Shape<D, K>::TOTAL - Shape<D, K>::OFF_TR) * sizeof(T) <= 96 * 1024 &&
+  return (size_t)(Shape<D, K>::TOTAL - Shape<D, K>::OFF_TR) * sizeof(T) <= 64 * 1024 &&
          (size_t)Shape<D, K>::TOTAL * sizeof(T) <= 100 * 1024;
 }
 

@@ -839,7 +839,7 @@ dg_status dg_mesh_create(int dim, int k, int64_t n_vert, const double* xyz, int6
     // leave the class-grouped tiles less than 3/4 full, as on meshes with arbitrary vertex
     // orders, and the facet tables fit in LDS; DGCONV_LANE_TABLES=0|1 overrides
     const double fill = (double)n_elem / (64.0 * std::max(1, m->h.ntiles));
-    const bool lane_ok = (m->t.total - m->t.off_tr) * 8 <= 96 * 1024 && m->t.total * 8 <= 100 * 1024;
+    const bool lane_ok = (m->t.total - m->t.off_tr) * 8 <= 64 * 1024 && m->t.total * 8 <= 100 * 1024;
     const char* lt = std::getenv("DGCONV_LANE_TABLES");
     const bool lane = lane_ok && (lt ? std::string(lt) == "1" : fill < 0.75);
     if (lane) dgmesh::use_lane_tables(m->h);
@@ -883,6 +883,20 @@ dg_status dg_volume_rule(int dim, int k, int* n_out, double* pts_out, double* wt
   if (!n_out) return fail(DG_EINVAL, "null pointer");
   std::vector<double> p, w;
   dgref::volume_rule<double>(dim, k, p, w);
+  *n_out = (int)w.size();
+  if (pts_out && wts_out) {
+    std::memcpy(pts_out, p.data(), p.size() * sizeof(double));
+    std::memcpy(wts_out, w.data(), w.size() * sizeof(double));
+  }
+  return DG_OK;
+}
+
+dg_status dg_facet_rule(int dim, int k, int* n_out, double* pts_out, double* wts_out) {
+  dg_status st = check_k(dim, k);
+  if (st != DG_OK) return st;
+  if (!n_out) return fail(DG_EINVAL, "null pointer");
+  std::vector<double> p, w;
+  dgref::operator_facet_rule<double>(dim, k, p, w);
   *n_out = (int)w.size();
   if (pts_out && wts_out) {
     std::memcpy(pts_out, p.data(), p.size() * sizeof(double));

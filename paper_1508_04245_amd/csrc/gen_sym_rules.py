@@ -1,13 +1,19 @@
-"""Writes volume_rules.hpp: the volume quadrature rules of the convection kernels.
+"""Writes sym_rules.hpp: the fully symmetric quadrature rules of the convection kernels.
 
-The volume integrand of the operator, (u (x) w) : grad(phi) for w, u and phi of degree k, is a
-polynomial of degree 3k-1, so any rule exact to that degree gives the same operator up to
-rounding.  The collapsed Gauss-Jacobi product rule needs ceil(3k/2)^d points; the fully
-symmetric rules below (invariant under every permutation of the simplex vertices, positive
-weights, every point inside the simplex) need fewer:
+Volume rules.  The volume integrand of the operator, (u (x) w) : grad(phi) for w, u and phi of
+degree k, is a polynomial of degree 3k-1, so any rule exact to that degree gives the same
+operator up to rounding.  The collapsed Gauss-Jacobi product rule needs ceil(3k/2)^d points;
+the fully symmetric rules below (invariant under every permutation of the simplex vertices,
+positive weights, every point inside the simplex) need fewer:
 
     2D  k = 1: 3 (collapsed 4)    k = 2: 7 (9)     k = 3: 16 (25)    k = 4: 28 (36)
     3D  k = 1: 4 (8)              k = 2: 14 (27)   k = 3: 46 (125)
+
+Facet rules (3D).  The upwind value is taken pointwise, so the facet rule is part of the
+operator's definition; on a triangular facet it is the symmetric rule of degree 3k where one
+needs fewer points than the collapsed rule with ceil((3k+1)/2)^2: k = 2 the 12-point degree-6
+rule, k = 3 the 19-point degree-9 rule of D. A. Dunavant (Int. J. Numer. Methods Eng. 21,
+1985), weights summing to 1.
 
 A rule is given by its orbits under the vertex permutations, each a barycentric generator
 with free parameters ('3' the centroid, '21' (a, a, 1-2a), '111' (a, b, 1-a-b); '4' the
@@ -20,10 +26,10 @@ of the monomials on the reference simplex,
     int x^i y^j = i! j! / (i+j+2)!,    int x^i y^j z^l = i! j! l! / (i+j+l+3)!,
 
 checks exactness to 1e-40, positive weights and interior points, and writes the expanded
-points (reference coordinates = barycentric coordinates 1..d) and weights (summing to the
-simplex measure) as long double literals.
+points (reference coordinates = barycentric coordinates 1..d) and weights as long double
+literals.
 
-    python gen_volume_rules.py > volume_rules.hpp
+    python gen_sym_rules.py > sym_rules.hpp
 """
 import itertools
 import sys
@@ -49,6 +55,15 @@ RULES = {
              ("31", [0.3150760322173066]), ("31", [0.030376367946228715]),
              ("22", [0.43884998942322245]), ("211", [0.022674246187050374, 0.22923965490894646]),
              ("211", [0.20580974356370157, 0.0162315274171111])],
+}
+
+# 3D facet rules, k: orbits on the triangle (degree 3k)
+FACET_RULES = {
+    2: [("21", [0.06308901449150214]), ("21", [0.24928674517090987]),
+        ("111", [0.053145049844816925, 0.3103524510337838])],
+    3: [("3", []), ("21", [0.04472951339445053]), ("21", [0.18820353561903191]),
+        ("21", [0.43708959149293103]), ("21", [0.4896825191987205]),
+        ("111", [0.036838412054736404, 0.221962989160761])],
 }
 
 
@@ -128,8 +143,7 @@ def residual(dim, spec, x, mons, exact):
     return r
 
 
-def refine(dim, k, spec):
-    deg = 3 * k - 1
+def refine(dim, deg, spec, n_collapsed):
     mons = monomials(dim, deg)
     exact = [exact_moment(e) for e in mons]
     x = [mp.mpf(v) for _, p in spec for v in p]
@@ -169,46 +183,66 @@ def refine(dim, k, spec):
         for b in orbit_points(dim, kind, p):
             pts.append(b[1:])
             wts.append(wo)
-    assert err < mp.mpf(10) ** -40, (dim, k, err)
-    assert all(v > 0 for v in wts), (dim, k)
-    assert all(min(b) > 0 and 1 - sum(b) > 0 for b in pts), (dim, k)
-    collapsed = max(1, (3 * k + 1) // 2) ** dim
-    assert len(wts) < collapsed, (dim, k)
+    assert err < mp.mpf(10) ** -40, (dim, deg, err)
+    assert all(v > 0 for v in wts), (dim, deg)
+    assert all(min(b) > 0 and 1 - sum(b) > 0 for b in pts), (dim, deg)
+    assert len(wts) < n_collapsed, (dim, deg)
     return pts, wts, err, npos
+
+
+def write_rule(out, name, title, pts, wts):
+    out.write("// %s\n" % title)
+    out.write("inline constexpr long double %s_pts[] = {\n" % name)
+    for b in pts:
+        out.write("    " + ", ".join(mp.nstr(v, 24, strip_zeros=False) + "L" for v in b) + ",\n")
+    out.write("};\ninline constexpr long double %s_wts[] = {\n" % name)
+    for v in wts:
+        out.write("    " + mp.nstr(v, 24, strip_zeros=False) + "L,\n")
+    out.write("};\n\n")
 
 
 def main():
     out = sys.stdout
-    out.write("// Generated by gen_volume_rules.py (fully symmetric volume rules exact to degree\n"
-              "// 3k-1 with positive weights and interior points); do not edit.\n"
+    out.write("// Generated by gen_sym_rules.py (fully symmetric quadrature rules with positive\n"
+              "// weights and interior points); do not edit.\n"
               "#pragma once\n\nnamespace dgref {\n\n")
-    entries = []
+    vol, fac = [], []
     for (dim, k), spec in sorted(RULES.items()):
-        pts, wts, err, _ = refine(dim, k, spec)
+        pts, wts, err, _ = refine(dim, 3 * k - 1, spec, max(1, (3 * k + 1) // 2) ** dim)
         name = "kVolRule%dd_k%d" % (dim, k)
-        out.write("// %dD, k = %d: degree %d, %d points (%s); max moment error %s\n"
-                  % (dim, k, 3 * k - 1, len(wts), " + ".join(s[0] for s in spec),
-                     mp.nstr(err, 3)))
-        out.write("inline constexpr long double %s_pts[] = {\n" % name)
-        for b in pts:
-            out.write("    " + ", ".join(mp.nstr(v, 24, strip_zeros=False) + "L" for v in b)
-                      + ",\n")
-        out.write("};\ninline constexpr long double %s_wts[] = {\n" % name)
-        for v in wts:
-            out.write("    " + mp.nstr(v, 24, strip_zeros=False) + "L,\n")
-        out.write("};\n\n")
-        entries.append((dim, k, len(wts), name))
+        write_rule(out, name, "volume %dD, k = %d: degree %d, %d points (%s); max moment error %s"
+                   % (dim, k, 3 * k - 1, len(wts), " + ".join(t[0] for t in spec), mp.nstr(err, 3)),
+                   pts, wts)
+        vol.append((dim, k, len(wts), name))
+    for k, spec in sorted(FACET_RULES.items()):
+        pts, wts, err, _ = refine(2, 3 * k, spec, max(1, (3 * k + 2) // 2) ** 2)
+        name = "kFacRule3d_k%d" % k
+        write_rule(out, name, "3D facet, k = %d: degree %d, %d points (%s), weights summing to 1; "
+                   "max moment error %s" % (k, 3 * k, len(wts), " + ".join(t[0] for t in spec),
+                                            mp.nstr(err, 3)), pts, [2 * v for v in wts])
+        fac.append((k, len(wts), name))
     out.write("// points of the symmetric volume rule for (dim, k), 0 where there is none\n"
               "constexpr int sym_vol_points(int dim, int k) {\n")
-    for dim, k, n, _ in entries:
+    for dim, k, n, _ in vol:
         out.write("  if (dim == %d && k == %d) return %d;\n" % (dim, k, n))
     out.write("  return 0;\n}\n\n")
     out.write("// the symmetric volume rule for (dim, k): points [n][dim], weights [n]; false if none\n"
               "inline bool sym_vol_rule(int dim, int k, const long double** pts,\n"
               "                         const long double** wts) {\n")
-    for dim, k, _, name in entries:
+    for dim, k, _, name in vol:
         out.write("  if (dim == %d && k == %d) { *pts = %s_pts; *wts = %s_wts; return true; }\n"
                   % (dim, k, name, name))
+    out.write("  return false;\n}\n\n")
+    out.write("// points of the symmetric 3D facet rule for k, 0 where there is none\n"
+              "constexpr int sym_facet_points(int k) {\n")
+    for k, n, _ in fac:
+        out.write("  if (k == %d) return %d;\n" % (k, n))
+    out.write("  return 0;\n}\n\n")
+    out.write("// the symmetric 3D facet rule for k: points (s, t) [n][2], weights [n] summing to 1;\n"
+              "// false if none\n"
+              "inline bool sym_facet_rule(int k, const long double** pts, const long double** wts) {\n")
+    for k, _, name in fac:
+        out.write("  if (k == %d) { *pts = %s_pts; *wts = %s_wts; return true; }\n" % (k, name, name))
     out.write("  return false;\n}\n\n}  // namespace dgref\n")
 
 

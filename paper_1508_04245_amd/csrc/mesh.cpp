@@ -401,7 +401,7 @@ void boundary_points(const Host& H, std::vector<double>& out) {
   using dgref::real;
   const int d = H.dim, nf = d + 1;
   std::vector<real> fp, fw;
-  dgref::facet_rule<real>(d, dgref::facet_points_1d(H.k), fp, fw);
+  dgref::operator_facet_rule<real>(d, H.k, fp, fw);
   const int nfq = (int)fw.size();
   out.assign((size_t)H.nbf * nfq * d, 0.0);
   for (int64_t b = 0; b < H.nbf; ++b) {
@@ -425,7 +425,7 @@ void build_tables(int dim, int k, Tables& T) {
   const int d = dim, np = dgref::n_basis(d, k);
   std::vector<real> vp, vw, fp, fw;
   dgref::volume_rule<real>(d, k, vp, vw);
-  dgref::facet_rule<real>(d, dgref::facet_points_1d(k), fp, fw);
+  dgref::operator_facet_rule<real>(d, k, fp, fw);
   T.nq = (int)vw.size();
   T.nfq = (int)fw.size();
   T.nperm = n_perm(d);

@@ -15,14 +15,14 @@
 // degree ascending, then r descending, then q descending.
 //
 // Quadrature: Gauss-Jacobi nodes by Newton iteration with polynomial deflation; collapsed
-// (Duffy) tensor rules on the simplex; the fully symmetric volume rules of volume_rules.hpp
-// (fewer points at the same degree) where there is one.  Everything is evaluated in long double and rounded to
+// (Duffy) tensor rules on the simplex; the fully symmetric volume and 3D facet rules of
+// sym_rules.hpp (fewer points at the same degree) where there is one.  Everything is evaluated in long double and rounded to
 // FP64 once, so the device tables are correctly rounded up to a few ulp.
 #pragma once
 #include <array>
 #include <cmath>
 #include <vector>
-#include "volume_rules.hpp"
+#include "sym_rules.hpp"
 
 namespace dgref {
 
@@ -230,9 +230,10 @@ inline void facet_rule(int dim, int n, std::vector<T>& pts, std::vector<T>& wts)
 }
 
 inline int vol_points_1d(int k) { int n = (3 * k + 1) / 2; return n < 1 ? 1 : n; }   // exact to 3k-1
+inline int facet_points_1d(int k) { int n = (3 * k + 2) / 2; return n < 1 ? 1 : n; } // exact to 3k
 
 // The volume rule of the operator, exact to degree 3k-1 (the degree of the volume integrand):
-// the fully symmetric rule of volume_rules.hpp where there is one, else the collapsed rule
+// the fully symmetric rule of sym_rules.hpp where there is one, else the collapsed rule
 // with vol_points_1d(k) points per direction.  Weights sum to |T^|.
 template <typename T>
 inline void volume_rule(int dim, int k, std::vector<T>& pts, std::vector<T>& wts) {
@@ -245,6 +246,21 @@ inline void volume_rule(int dim, int k, std::vector<T>& pts, std::vector<T>& wts
   }
   collapsed_rule<T>(dim, vol_points_1d(k), pts, wts);
 }
-inline int facet_points_1d(int k) { int n = (3 * k + 2) / 2; return n < 1 ? 1 : n; } // exact to 3k
+
+// The facet rule of the operator, exact to degree 3k, weights summing to 1 (part of the
+// operator's definition, the upwind value being taken pointwise): 2D facet_rule with
+// facet_points_1d(k) points; 3D the symmetric rule of sym_rules.hpp where there is one (k = 2,
+// 3), else the collapsed facet_rule with facet_points_1d(k)^2 points.
+template <typename T>
+inline void operator_facet_rule(int dim, int k, std::vector<T>& pts, std::vector<T>& wts) {
+  const long double *p = nullptr, *w = nullptr;
+  if (dim == 3 && sym_facet_rule(k, &p, &w)) {
+    const int n = sym_facet_points(k);
+    pts.assign(p, p + (size_t)n * 2);
+    wts.assign(w, w + n);
+    return;
+  }
+  facet_rule<T>(dim, facet_points_1d(k), pts, wts);
+}
 
 }  // namespace dgref

@@ -329,3 +329,18 @@ def test_volume_rule_exact_to_the_volume_integrand_degree(dim, k):
                 assert pb in key and abs(key[pb] - w) <= 1e-15, (perm, b)
     m = dg.Mesh.box(dim, 2 if dim == 3 else 3, k)
     assert m.info["nq_vol"] == len(wts)
+
+
+@pytest.mark.parametrize("dim,k", [(2, 2), (2, 4), (3, 1), (3, 2), (3, 3), (3, 4)])
+def test_facet_rule_matches_the_oracle(dim, k):
+    """The library's facet rule (part of the operator's definition) is the oracle's point set
+    with the oracle's weights (the order of the points may differ)."""
+    pts, wts = dg.facet_rule(dim, k)
+    op, ow = R.operator_facet_rule(dim, k)
+    assert pts.shape == op.shape and abs(wts.sum() - 1.0) < 1e-15
+    key = {tuple(np.round(p, 12)): w for p, w in zip(op, ow)}
+    for p, w in zip(pts, wts):
+        kp = tuple(np.round(p, 12))
+        assert kp in key and abs(key[kp] - w) < 1e-15, (p, w)
+    m = dg.Mesh.box(dim, 2 if dim == 3 else 3, k)
+    assert m.info["nq_facet"] == len(wts)

@@ -96,3 +96,27 @@ def test_basis_counts_and_order():
     assert R.n_basis(2, 4) == 15 and R.n_basis(3, 3) == 20 and R.n_basis(3, 2) == 10
     assert R.basis_indices(2, 1) == [(0, 0), (0, 1), (1, 0)]
     assert R.basis_indices(3, 1) == [(0, 0, 0), (0, 0, 1), (0, 1, 0), (1, 0, 0)]
+
+
+@pytest.mark.parametrize("k,npts", [(2, 12), (3, 19)])
+def test_symmetric_facet_rule(k, npts):
+    """The 3D operator's facet rule for k = 2, 3: exact to degree 3k and not beyond, weights
+    summing to 1, positive weights, points inside the triangle, invariant under the six
+    permutations of the triangle's vertices, fewer points than the collapsed rule."""
+    import itertools
+    p, w = R.operator_facet_rule(3, k)
+    assert len(w) == npts < R.facet_points(k) ** 2
+    assert abs(w.sum() - 1.0) < 1e-15 and np.all(w > 0)
+    bary = np.concatenate([1 - p.sum(1, keepdims=True), p], 1)
+    assert bary.min() > 0
+    for e in monomial_exponents(2, 3 * k):
+        val = np.sum(w * np.prod(p ** np.array(e), axis=1))
+        assert abs(val - 2.0 * exact_monomial(e)) < 1e-15, (e, val)
+    errs = [abs(np.sum(w * np.prod(p ** np.array(e), axis=1)) - 2.0 * exact_monomial(e))
+            for e in monomial_exponents(2, 3 * k + 1) if sum(e) == 3 * k + 1]
+    assert max(errs) > 1e-10
+    key = {tuple(np.round(b, 12)): x for b, x in zip(bary, w)}
+    for perm in itertools.permutations(range(3)):
+        for b, x in zip(bary, w):
+            pb = tuple(np.round(b[list(perm)], 12))
+            assert pb in key and abs(key[pb] - x) < 1e-15
