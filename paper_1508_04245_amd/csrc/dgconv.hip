@@ -160,13 +160,16 @@ hipError_t launch_maxvel(const dg_mesh* m, const double* a, double* partial, hip
 // table in LDS; other tables too large for LDS all come through scalar loads.
 template <int D, int K, typename T, bool SELF = true, bool BND = false>
 constexpr int default_tab_src() {
-  // 3D P2 (70 KiB of tables): basis values and gradients in LDS, traces and lifts through
-  // scalar loads, for the FP64 self kernel (753 against 799 us per launch with every table
-  // through scalar loads); the frozen and boundary variants keep scalar loads
-  if (D == 3 && K == 2 && sizeof(T) == 8 && SELF && !BND) return 28;
-  // FP32 self kernels: 3D P2 with basis values and neighbour traces in LDS (410 against 473
-  // us with every table in LDS); 2D P4 with the lifts through scalar loads (35.0 against 36.2)
-  if (D == 3 && K == 2 && sizeof(T) == 4 && SELF && !BND) return 22;
+  // 3D P2 (14 volume and 12 facet points, 49 KiB of tables): the FP64 self kernel with the
+  // basis values in LDS and every other table through scalar loads (496 us per launch
+  // against 507 with every table through scalar loads, 519 for basis values and gradients in
+  // LDS, 526 for 22, 616 with every table in LDS); the frozen and boundary variants keep
+  // scalar loads
+  if (D == 3 && K == 2 && sizeof(T) == 8) return SELF && !BND ? 30 : dgk::SM_ALL;
+  // FP32 self kernels: 3D P2 with basis values and gradients in LDS (285.5 against 289.5 us
+  // for 22, 287 with every table through scalar loads, 328 with every table in LDS); 2D P4
+  // with the lifts through scalar loads (35.0 against 36.2)
+  if (D == 3 && K == 2 && sizeof(T) == 4 && SELF && !BND) return 28;
   if (D == 2 && K == 4 && sizeof(T) == 4 && SELF && !BND) return 16;
   if (!dgk::tables_in_lds<D, K, T>()) return dgk::SM_ALL;
   if (D == 2 && K == 4 && sizeof(T) == 8) return 22;
@@ -199,6 +202,7 @@ constexpr int lane_tab_src() {
   // 2D P4 FP64: the weighted gradients through scalar loads (jittered 256x256x2: 51.4 against
   // 52.3 us per launch with every table in LDS; the basis values too: 84 us)
   if (D == 2 && K == 4 && sizeof(T) == 8) return 1 << dgk::TB_DV;
+  if (D == 3 && K == 2 && sizeof(T) == 8) return (1 << dgk::TB_BV) | (1 << dgk::TB_DV);
   return (size_t)dgk::Shape<D, K>::TOTAL * sizeof(T) <= 65536 ? 0
                                                               : (1 << dgk::TB_BV) | (1 << dgk::TB_DV);
 }
