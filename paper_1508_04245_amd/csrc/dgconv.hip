@@ -154,10 +154,12 @@ hipError_t launch_maxvel(const dg_mesh* m, const double* a, double* partial, hip
 
 // default table sources of the VALU kernel (bit t of the mask: table t read through scalar
 // loads, else from LDS; t = basis values, gradients, own traces, neighbour traces, lifts),
-// from sweeps of the masks on MI355X.  2D P4: basis values and neighbour traces in LDS, the
-// rest through scalar loads (mask 22: 48.3 us per launch on 256x256x2 triangles, against
-// 49.4 for 21, 57.6 with every table in LDS and 88 with none).  Smaller elements keep every
-// table in LDS; other tables too large for LDS all come through scalar loads.
+// from sweeps of the masks on MI355X.  2D P4 FP64 (28 volume points): basis values and lifts
+// in LDS, gradients and both trace tables through scalar loads (mask 14: 41.2-41.3 us per
+// launch on 256x256x2 triangles, against 41.6-41.7 for 22, 44.1 for 26, 48.2 for 20, 49.1-
+// 49.5 for 2, 18 and 30, 52 for 6, 53.5 for 21, 57 for 28, 58 with every table in LDS and 78
+// with none).  Smaller elements keep every table in LDS; other tables too large for LDS all
+// come through scalar loads.
 template <int D, int K, typename T, bool SELF = true, bool BND = false>
 constexpr int default_tab_src() {
   // 3D P2 (14 volume and 12 facet points, 49 KiB of tables): the FP64 self kernel with the
@@ -172,7 +174,7 @@ constexpr int default_tab_src() {
   if (D == 3 && K == 2 && sizeof(T) == 4 && SELF && !BND) return 28;
   if (D == 2 && K == 4 && sizeof(T) == 4 && SELF && !BND) return 16;
   if (!dgk::tables_in_lds<D, K, T>()) return dgk::SM_ALL;
-  if (D == 2 && K == 4 && sizeof(T) == 8) return 22;
+  if (D == 2 && K == 4 && sizeof(T) == 8) return 14;
   return 0;
 }
 
