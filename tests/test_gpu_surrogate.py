@@ -57,6 +57,24 @@ def test_features_and_targets(env):
     assert np.abs(t - tref).max() <= 1e-6 * np.abs(tref).max()
 
 
+@pytest.mark.parametrize("B", [1, 15, 64, 65, 129])
+def test_fused_forward_ragged_batches(env, B):
+    """The fused inference kernel (64 rows per workgroup, 16-row tiles) on batch sizes that
+    leave a block or a tile partly empty: every row against the FP64 network oracle, at the
+    bar of the full-batch forward check."""
+    dg, S, mesh, sur = env
+    say("case fused forward, batch %d" % B)
+    p = mlp.init_params(7).astype(np.float32)
+    sur.load(p)
+    x = np.random.default_rng(8 + B).normal(size=(B, 80)).astype(np.float32)
+    y = sur.forward(torch.tensor(x, device="cuda")).cpu().numpy()
+    yref = mlp.forward(p.astype(np.float64), x.astype(np.float64))
+    assert np.all(np.isfinite(y))
+    e = rel(y, yref)
+    say("   rel %.3e" % e)
+    assert e < 3e-2
+
+
 def test_forward_and_gradient_vs_oracle(env):
     dg, S, mesh, sur = env
     say("case surrogate forward/gradient")

@@ -136,6 +136,16 @@ def test_error_paths():
     with pytest.raises(dg.DGError) as e:
         dg.Mesh.from_arrays(2, 1, xyz, bad, np.ones(2))
     assert e.value.status == -1
+    # rule queries: dimension, degree, missing count pointer
+    L = dg.lib()
+    for fn in (L.dg_volume_rule, L.dg_facet_rule):
+        n = ctypes.c_int(-7)
+        assert fn(4, 1, ctypes.byref(n), None, None) == -1
+        assert fn(3, 5, ctypes.byref(n), None, None) == -4
+        assert fn(2, 7, ctypes.byref(n), None, None) == -4
+        assert fn(2, 2, None, None, None) == -1
+        assert n.value == -7  # nothing written on an error
+        assert fn(2, 2, ctypes.byref(n), None, None) == 0 and n.value > 0
 
 
 @pytest.mark.parametrize("name", ["dubiner_2d_k3.txt", "dubiner_3d_k2.txt"])
