@@ -54,15 +54,18 @@ def kernel_sources_hash():
     return h.hexdigest()[:16]
 
 
-def kernel_label(cfg, precision, fp64_kernel):
+def kernel_label(cfg, precision, fp64_kernel, n_tiles=None):
     """Which operator kernel the library runs (its default: matrix cores for FP64 when the
-    element has >= 20 basis functions per component, and for 2D P3)."""
+    element has >= 20 basis functions per component, and for 2D P3; on the VALU, two lanes per
+    element for 2D P2-P4 meshes of fewer than 1024 tiles)."""
     NP, _, _ = shape_counts(cfg["dim"], cfg["k"])
     if precision == "fp64":
         kind = fp64_kernel or ("mfma" if NP >= 20 or (cfg["dim"], cfg["k"]) == (2, 3) else "valu")
     else:
         kind = "valu" if precision in ("fp32", "mixf32") else "mfma"
     if kind == "valu" and precision == "fp64":
+        if cfg["dim"] == 2 and 2 <= cfg["k"] <= 4 and n_tiles is not None and n_tiles < 1024:
+            return kind, "conv_pair_kernel<2,%d>" % cfg["k"]
         return kind, "conv_self_kernel<%d,%d>" % (cfg["dim"], cfg["k"])  # the pipelined path
     name = "conv_kernel" if kind == "valu" else "mconv_kernel"
     return kind, "%s<%d,%d,%s,self>" % (name, cfg["dim"], cfg["k"], precision)
@@ -573,7 +576,7 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     apply_s = ev0.elapsed_time(ev1) / 1e3 / n_app
-    kind, label = kernel_label(cfg, args.precision, args.fp64_kernel)
+    kind, label = kernel_label(cfg, args.precision, args.fp64_kernel, m.info["n_tiles"])
     tr = MEASURED_TRAFFIC.get((args.config, args.precision, kind))
     traffic = (tr[0] if tr and not args.n and args.mesh == "box" and tr[1] == kernel_sources_hash()
                else None)

@@ -760,4 +760,148 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, double>(), 8))) conv_self_ker
   }
 }
 
+// The partner lane's value within a lane pair (2j, 2j + 1): DPP quad permutation [1, 0, 3, 2],
+// two 32-bit moves for a double.
+__device__ __forceinline__ double pair_swap(double x) {
+  const long long v = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(v & 0xffffffffll), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), 0xB1, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 2D FP64 self-convection on a periodic mesh with tiles of one element class, two lanes per
+// element: lane pair (2j, 2j + 1) of a wave holds element j of one half (32 elements) of a
+// 64-element tile, lane 2j + h its velocity component h (coefficients, the sums R, the neighbour
+// coefficients), so a tile takes two waves and a workgroup of four waves two tiles.  At a point,
+// each lane interpolates its component, takes the partner's by a DPP exchange, and contracts
+// the flux row w_h (J^-1 w) with the test gradients into its own sums; on a facet each lane
+// forms the traces of its component, exchanges them, and both lanes form the normal speed
+// as the sum of the two component products (a + b, rounded alike in both lanes).  Twice the
+// waves of conv_self_kernel at 30 coefficients of state per lane instead of 60.  Modes 0 and 1.
+template <int K, int SM>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(4, 8))) conv_pair_kernel(ConvArgs<double> A) {
+  constexpr int D = 2;
+  using S = Shape<D, K>;
+  using T = double;
+  constexpr int NP = S::NP;
+  typedef const int __attribute__((address_space(4)))* ciptr;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, h = lane & 1;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int tile = __builtin_amdgcn_readfirstlane(blk * 2 + (wv >> 1));
+  static_assert(SM == SM_ALL || staged_fits<D, K, T, SM>(), "staged tables exceed 64 KiB");
+  constexpr int LO = SM == SM_ALL ? 0 : staged_lo<D, K, SM>();
+  Tabs<SM, T, LO> tab;
+  tab.c = (typename Tabs<SM, T, LO>::cptr)A.tab;
+  if constexpr (SM != SM_ALL) {
+    __shared__ T stab[staged_hi<D, K, SM>() - LO];
+    stage_tables<D, K, SM>(stab, A.tab);
+    __syncthreads();
+    tab.l = stab;
+  } else {
+    tab.l = A.tab;
+  }
+  if (tile >= A.ntiles) return;
+  const int type = __builtin_amdgcn_readfirstlane(A.tile_type[tile]);
+  if (type < 0) return;  // empty tile padding a block
+  const int slot = tile * 64 + (wv & 1) * 32 + (lane >> 1);
+  const int e_raw = A.elem_list[slot];
+  const int e = e_raw >= 0 ? e_raw : A.elem_list[tile * 64];  // padded pairs redo element 0
+  const ciptr ttab = (ciptr)A.type_tab;
+
+  T c[NP], R[NP], jo[D], jt[D];  // own component; J^-1 columns h and 1 - h
+  int nbv[D + 1];
+  {
+    const T* __restrict__ p = A.x + (size_t)e * D * NP + h * NP;
+#pragma unroll
+    for (int m = 0; m < NP; ++m) c[m] = p[m];
+    const T* __restrict__ pj = A.jinv + (size_t)e * D * D;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const T j0 = pj[a * D], j1 = pj[a * D + 1];
+      jo[a] = h ? j1 : j0;
+      jt[a] = h ? j0 : j1;
+    }
+#pragma unroll
+    for (int f = 0; f <= D; ++f) nbv[f] = A.nbr[(size_t)e * (D + 1) + f];
+  }
+#pragma unroll
+  for (int m = 0; m < NP; ++m) R[m] = T(0);
+
+  // volume term: R_hm += w_h(x_q) (J^-1 w(x_q)) . w_q grad^ phi_m
+#pragma unroll 1
+  for (int q = 0; q < S::NQ; ++q) {
+    const int bq = S::OFF_BV + q * NP;
+    const int dq = S::OFF_DV + q * NP * D;
+    T wh = T(0);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) wh = fma(tab.template get<TB_BV>(bq + m), c[m], wh);
+    const T wo = pair_swap(wh);
+    const T g0 = wh * fma(jo[0], wh, jt[0] * wo);
+    const T g1 = wh * fma(jo[1], wh, jt[1] * wo);
+#pragma unroll
+    for (int m = 0; m < NP; ++m)
+      R[m] = fma(g0, tab.template get<TB_DV>(dq + m * D), fma(g1, tab.template get<TB_DV>(dq + m * D + 1), R[m]));
+  }
+
+  // facets: pointwise upwind flux with the neighbour across local facet f
+#pragma unroll
+  for (int f = 0; f <= D; ++f) {
+    T cn[NP];
+    {
+      const T* __restrict__ p = A.x + (size_t)nbv[f] * D * NP + h * NP;
+#pragma unroll
+      for (int m = 0; m < NP; ++m) cn[m] = p[m];
+    }
+    const int tt = ttab[type * (D + 1) + f];
+    const int own = __builtin_amdgcn_readfirstlane(tt & 0xffff);
+    const int nbt = __builtin_amdgcn_readfirstlane(tt >> 16);
+    const int tro = S::OFF_TR + own * S::NFQ * NP;
+    const int trn = S::OFF_TR + nbt * S::NFQ * NP;
+    const int lfo = S::OFF_LF + own * S::NFQ * NP;
+    T Nh = T(0);  // component h of the scaled normal J^-T n^
+#pragma unroll
+    for (int a = 0; a < D; ++a) Nh = fma(jo[a], nref<D, T>(f, a), Nh);
+#pragma unroll 1
+    for (int q = 0; q < S::NFQ; ++q) {
+      T wm = T(0), wp = T(0);
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        wm = fma(tab.template get<TB_TRO>(tro + q * NP + m), c[m], wm);
+        wp = fma(tab.template get<TB_TRN>(trn + q * NP + m), cn[m], wp);
+      }
+      // b = bb / 2 with bb = sum_j (wm_j + wp_j) Nt_j;  F = b (wm + wp) / 2 + |b| (wm - wp) / 2
+      const T th = (wm + wp) * Nh;
+      const T bb = th + pair_swap(th);
+      const T hb = T(0.25) * bb;
+      const T ha = T(0.25) * fabs(bb);
+      const T F = hb * (wm + wp) + ha * (wm - wp);
+#pragma unroll
+      for (int m = 0; m < NP; ++m) R[m] = fma(-tab.template get<TB_LF>(lfo + q * NP + m), F, R[m]);
+    }
+  }
+
+  if (e_raw < 0) return;
+  T* o = A.out + (size_t)e * D * NP + h * NP;
+  if (A.mode == 0) {
+#pragma unroll
+    for (int m = 0; m < NP; ++m) o[m] = R[m];
+  } else {
+    const T a = A.a, b = A.b, dt = A.dt;
+    if (a != T(0)) {
+      // all loads of w0 before any store: out may be w0 itself (in-place last stage)
+      const T* pw = A.w0 + (size_t)e * D * NP + h * NP;
+      T w0v[NP];
+#pragma unroll
+      for (int m = 0; m < NP; ++m) w0v[m] = pw[m];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int m = 0; m < NP; ++m) o[m] = fma(a, w0v[m], b * fma(dt, R[m], c[m]));
+    } else {
+#pragma unroll
+      for (int m = 0; m < NP; ++m) o[m] = b * fma(dt, R[m], c[m]);
+    }
+  }
+}
+
 }  // namespace dgk

@@ -234,6 +234,16 @@ hipError_t launch_conv_dk(const dg_mesh* m, const dgk::ConvArgs<TS, T>& a, hipSt
   // scalar loads (31) and, where the whole block fits in LDS, every table in LDS (0), 21
   // (gradients and neighbour traces in LDS) or 22; other values keep the default
   if constexpr (SELF && sizeof(T) == 8 && sizeof(TS) == 8) {
+    if constexpr (D == 2 && K >= 2 && K <= 4) {  // two lanes per element (mesh option)
+      if (m->pair && a.mode != 2) {
+        // table sources at four waves per SIMD: every table in LDS up to P3; for P4 the LDS
+        // return bandwidth of the broadcast reads limits, and only the basis values stay there
+        constexpr int kPair = K == 4 ? 30 : 0;
+        hipLaunchKernelGGL((dgk::conv_pair_kernel<K, kPair>), dim3(m->h.ntiles / 2), dim3(256),
+                           0, s, a);
+        return hipGetLastError();
+      }
+    }
     const int src = m->tab_src;
     if (src >= 0 && src != kDef) {
       if (src == dgk::SM_ALL) {
@@ -861,6 +871,13 @@ dg_status dg_mesh_create(int dim, int k, int64_t n_vert, const double* xyz, int6
     // DGCONV_SELF_PIPE=0 takes the general kernel
     const char* sp = std::getenv("DGCONV_SELF_PIPE");
     m->self_pipe = !(sp && std::string(sp) == "0");
+    // Two lanes per element for the 2D FP64 self-convection kernel (P2 to P4) on meshes with
+    // fewer than 1024 tiles, which leave SIMDs idle with one lane per element: 2D 16x16x2 P2
+    // 7.44 -> 5.36 us per launch.  On full meshes it loses (2D 256x256x2 P4: 43.2 against 41.6
+    // us; 2D 128x128x2 P3: 11.2-11.3, as the matrix-core kernel).  DGCONV_PAIR=0|1 overrides
+    const char* pr = std::getenv("DGCONV_PAIR");
+    m->pair = pr ? std::string(pr) == "1"
+                 : dim == 2 && k >= 2 && k <= 4 && m->h.ntiles < 1024 && !lane && m->h.nbf == 0;
   }
   *out = m;
   return DG_OK;

@@ -50,7 +50,8 @@ struct dg_mesh {
   int tab_src = -1;  // VALU kernel table sources (bit t: table t via scalar loads); -1: default
   bool fp64_mfma = false;   // FP64 self-convection on the matrix cores instead of the VALU kernel
   bool fp64_mfma_frozen = false;  // the same for a given (frozen or extrapolated) velocity
-  bool self_pipe = true;  // FP64 self-convection on the VALU: the pipelined kernel (conv_self_kernel)
+  bool self_pipe = true;
+  bool pair = false;          // 2D FP64 self-convection with two lanes per element  // FP64 self-convection on the VALU: the pipelined kernel (conv_self_kernel)
   // matrix-core path: 16-wide tiles and fragment tables per contraction engine
   int* d_elem_list16 = nullptr;
   int* d_tile_type16 = nullptr;
