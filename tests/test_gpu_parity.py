@@ -118,7 +118,8 @@ def full_case(cfg, field):
 
 # (configuration, field, precision)
 FULL_CASES = [
-    (C2, "tg", "fp64"), (C2, "tg", "fp32"),
+    (C2, "tg", "fp64"), (C2, "tg", "fp32"), (C2, "tg", "mixf32"), (C2, "tg", "f16x2"),
+    (C2, "tg", "bf16x3"),
     (C3, "tg", "fp64"), (C3, "tg", "f16x2"), (C3, "tg", "bf16x3"),
     (C4, "fourier", "fp64"), (C4, "fourier", "fp32"), (C4, "fourier", "mixf32"),
     (C4, "fourier", "f16x2"), (C4, "fourier", "bf16x3"),
