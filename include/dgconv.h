@@ -347,7 +347,8 @@ dg_status dg_eval_basis(int dim, int k, int64_t n_pts, const double* pts, double
  * wts_out [n] summing to the reference simplex measure (1/2, 1/6).  A fully symmetric rule
  * with positive weights and interior points where the library has one (2D k 1..4,
  * 3D k 1..3), else the collapsed Gauss-Jacobi rule with ceil(3k/2)^dim points.  Host only.
- * Errors: DG_EINVAL (dim, k out of range, n_out NULL). */
+ * Errors: DG_EINVAL (dim not 2/3, k < 0, n_out NULL), DG_EUNSUPPORTED (k above the compiled
+ * range); *n_out is written only on success. */
 dg_status dg_volume_rule(int dim, int k, int* n_out, double* pts_out, double* wts_out);
 
 /* The facet quadrature rule of the operator's facet terms (Sec. 2.3, the facet integrals of
@@ -357,7 +358,8 @@ dg_status dg_volume_rule(int dim, int k, int* n_out, double* pts_out, double* wt
  * t (C - A) of the facet's canonically ordered vertices) and wts_out [n] summing to 1.  2D:
  * ceil((3k+1)/2) Gauss-Legendre points; 3D: the fully symmetric rule of degree 3k for k = 2
  * (12 points) and k = 3 (19 points), else the collapsed rule with ceil((3k+1)/2)^2 points.
- * Host only.  Errors: DG_EINVAL (dim, k out of range, n_out NULL). */
+ * Host only.  Errors: DG_EINVAL (dim not 2/3, k < 0, n_out NULL), DG_EUNSUPPORTED (k above
+ * the compiled range); *n_out is written only on success. */
 dg_status dg_facet_rule(int dim, int k, int* n_out, double* pts_out, double* wts_out);
 
 const char* dg_last_error(void);
