@@ -345,7 +345,7 @@ dg_status dg_eval_basis(int dim, int k, int64_t n_pts, const double* pts, double
  * change the operator): *n_out = number of points; if pts_out and wts_out are not NULL,
  * host pts_out [n][dim] in reference coordinates (= barycentric coordinates 1..dim) and
  * wts_out [n] summing to the reference simplex measure (1/2, 1/6).  A fully symmetric rule
- * with positive weights and interior points where the library has one (2D k 1..4,
+ * with positive weights and interior points where the library has one (2D k 1..5,
  * 3D k 1..3), else the collapsed Gauss-Jacobi rule with ceil(3k/2)^dim points.  Host only.
  * Errors: DG_EINVAL (dim not 2/3, k < 0, n_out NULL), DG_EUNSUPPORTED (k above the compiled
  * range); *n_out is written only on success. */

@@ -7,6 +7,7 @@ the fully symmetric rules below (invariant under every permutation of the simple
 positive weights, every point inside the simplex) need fewer:
 
     2D  k = 1: 3 (collapsed 4)    k = 2: 7 (9)     k = 3: 16 (25)    k = 4: 28 (36)
+        k = 5: 42 (64)
     3D  k = 1: 4 (8)              k = 2: 14 (27)   k = 3: 46 (125)
 
 Facet rules (3D).  The upwind value is taken pointwise, so the facet rule is part of the
@@ -48,6 +49,13 @@ RULES = {
              ("21", [0.029132577733838472]), ("21", [0.4964082121896513]),
              ("21", [0.43821104894017354]), ("111", [0.009252951305720096, 0.1518192044856569]),
              ("111", [0.0463970358405466, 0.29407958108856036])],
+    (2, 5): [("21", [0.06179988309089579]), ("21", [0.4176447193403893]),
+             ("21", [0.2734775283089308]), ("21", [0.019390961248661156]),
+             ("21", [0.17720553241294396]), ("21", [0.4889639103622024]),
+             ("111", [0.09291624935686842, 0.3368614597964482]),
+             ("111", [0.17226668782115825, 0.7706085547747088]),
+             ("111", [0.11897449769695961, 0.8797571713697192]),
+             ("111", [0.014646950055685488, 0.6869801678083242])],
     (3, 1): [("31", [0.1381966011250105])],
     (3, 2): [("31", [0.3108859192633004]), ("31", [0.0927352503108908]),
              ("22", [0.04550370412565067])],

@@ -329,7 +329,7 @@ def test_volume_rule_exact_to_the_volume_integrand_degree(dim, k):
         assert abs(got - ex) <= 2e-15 * ex * max(1, len(wts)) ** 0.5, (e, got, ex)
     bary = np.concatenate([1 - pts.sum(1, keepdims=True), pts], 1)
     assert np.all(wts > 0) and bary.min() > 0
-    symmetric = (dim, k) in [(2, 1), (2, 2), (2, 3), (2, 4), (3, 1), (3, 2), (3, 3)]
+    symmetric = (dim, k) in [(2, 1), (2, 2), (2, 3), (2, 4), (2, 5), (3, 1), (3, 2), (3, 3)]
     if symmetric:
         assert len(wts) < n_coll
         key = {tuple(np.round(b, 12)): w for b, w in zip(bary, wts)}
