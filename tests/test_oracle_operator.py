@@ -370,3 +370,24 @@ def test_richardson_stops_at_once_on_a_zero_residual():
     g = np.zeros(sp.shape)
     out, n, hist = sp.richardson(g, U, 0.3, 0.5, 1e-8, 100)
     assert n == 0 and hist == [0.0] and not out.any()
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_symmetric_facet_rule_changes_only_kinked_facets(k):
+    """The 3D facet rule for k = 2, 3 (the symmetric rule of degree 3k) and the collapsed rule
+    of the same degree give the same operator wherever the facet integrand is a polynomial:
+    for a frozen constant convecting field beta keeps its sign on every facet, and the two
+    operators agree to rounding; for self-convection of a field whose normal speed changes
+    sign inside facets they differ (the upwind value is taken pointwise)."""
+    from oracle import refelem as R
+    sp = Space(box_mesh(3, 2, jitter=0.1, seed=3), k)
+    w = np.random.default_rng(5).normal(size=sp.shape)
+    u = np.zeros(sp.shape)
+    u[:, :, 0] = np.array([0.7, -0.4, 0.3]) / np.sqrt(6.0)  # the constant c: c / phi_0
+    sc = Space(box_mesh(3, 2, jitter=0.1, seed=3), k)
+    sc.fq, sc.fw = R.facet_rule(3, R.facet_points(k))
+    assert len(sp.fw) < len(sc.fw)
+    a, b = sp.apply(w, u), sc.apply(w, u)
+    assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
+    a, b = sp.apply(w), sc.apply(w)
+    assert np.abs(a - b).max() > 1e-8 * np.abs(b).max()
