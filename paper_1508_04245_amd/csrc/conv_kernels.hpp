@@ -550,7 +550,8 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, T>(), 8))) conv_kernel(ConvAr
 // the volume loop cut into D + 2 pieces and the facets between them.  The neighbour state of
 // each facet is requested before the volume piece that precedes it, so its memory latency
 // overlaps that piece (the registers of one neighbour state are free during the volume loop),
-// and the volume and facet terms accumulate into one set of sums.
+// and the volume and facet terms accumulate into one set of sums.  The Runge-Kutta base
+// state takes the neighbour registers after the last facet, before the last volume piece.
 template <int D, int K, int SM>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(min_waves<D, K, double>(), 8))) conv_self_kernel(ConvArgs<double> A) {
@@ -606,13 +607,14 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, double>(), 8))) conv_self_ker
 
   // neighbour state of the facet about to come
   T cn[D][NP];
-  auto load_nbr_state = [&](int ne) {
-    const T* __restrict__ p = A.x + (size_t)ne * D * NP;
+  auto load_nbr_state_from = [&](const T* __restrict__ src, int ne) {
+    const T* __restrict__ p = src + (size_t)ne * D * NP;
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
       for (int m = 0; m < NP; ++m) cn[i][m] = p[i * NP + m];
   };
+  auto load_nbr_state = [&](int ne) { load_nbr_state_from(A.x, ne); };
 
   // volume term over the points [q0, q1): R[i][m] += w_i(x_q) (J^-1 w(x_q)) . w_q grad^ phi_m
   auto volume = [&](int q0, int q1) {
@@ -696,7 +698,9 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, double>(), 8))) conv_self_ker
     }
   };
 
-  constexpr int NCH = D + 2;
+  // D + 3 shares of the volume points: one before each facet, two after the last facet, where
+  // the base state's latency must be covered as well
+  constexpr int NCH = D + 3;
   load_nbr_state(nbv[0]);
 #pragma unroll
   for (int f = 0; f <= D; ++f) {
@@ -704,17 +708,16 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, double>(), 8))) conv_self_ker
     facet(f);
     if (f < D) load_nbr_state(nbv[f + 1]);
   }
+  // the base state w0 of the stage goes into the registers of the last neighbour state,
+  // requested before the last volume piece so that its latency overlaps that piece
+  const bool base = A.mode == 2 || (A.mode == 1 && A.a != T(0));
+  if (base) load_nbr_state_from(A.w0, e);
   volume((D + 1) * S::NQ / NCH, S::NQ);
 
   T* o = A.out + (size_t)e * D * NP;
   if (A.mode == 2) {
     // every lane takes part in the wave sum; padded lanes store nothing and add zero
-    const T* pg = A.w0 + (size_t)e * D * NP;
-    T gv[D][NP];
-#pragma unroll
-    for (int i = 0; i < D; ++i)
-#pragma unroll
-      for (int m = 0; m < NP; ++m) gv[i][m] = pg[i * NP + m];
+    const T(&gv)[D][NP] = cn;  // w0
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < D; ++i)
@@ -737,14 +740,10 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, double>(), 8))) conv_self_ker
   } else {
     const T a = A.a, b = A.b, dt = A.dt;
     if (a != T(0)) {
-      // all loads of w0 before any store: out may be w0 itself (in-place last stage), and
-      // back-to-back stores let whole cache lines complete in L2 before eviction
-      const T* pw = A.w0 + (size_t)e * D * NP;
-      T w0v[D][NP];
-#pragma unroll
-      for (int i = 0; i < D; ++i)
-#pragma unroll
-        for (int m = 0; m < NP; ++m) w0v[i][m] = pw[i * NP + m];
+      // w0 (in cn) was loaded before the last volume piece, so before any store: out may be
+      // w0 itself (in-place last stage), and back-to-back stores let whole cache lines
+      // complete in L2 before eviction
+      const T(&w0v)[D][NP] = cn;
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int i = 0; i < D; ++i)
