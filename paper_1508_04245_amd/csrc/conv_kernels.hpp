@@ -727,7 +727,10 @@ __attribute__((amdgpu_waves_per_eu(min_waves<D, K, double>(), 8))) conv_self_ker
         if (e_raw >= 0) o[i * NP + m] = fma(A.ds, res, c[i][m]);
         acc = fma(res, res, acc);
       }
-    acc = wave_sum(e_raw >= 0 ? acc * A.absdet[e] : 0.0);
+    // the element index is read again here (volatile; e_raw once more), so that no 64-bit
+    // offset stays live in registers through the loops for this one use
+    const int e_sum = *(volatile const int*)(A.elem_list + tile * 64 + lane);
+    acc = wave_sum(e_sum >= 0 ? acc * A.absdet[e_sum >= 0 ? e_sum : 0] : 0.0);
     if (lane == 0) A.partial[tile] = acc;
     return;
   }
