@@ -33,9 +33,11 @@ PEAK_FP32 = 157.3e12
 PEAK_HBM = 8.0e12
 
 # HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs (FETCH_SIZE x2.00,
-# WRITE_SIZE x1.00: the factors a plain 512 MiB device copy gives), mean over the launches of
-# SSP-RK3 substeps; keyed by (config, precision, kernel) with the SHA-256 of the kernel sources
-# the counters were taken on.  Reported as null once those sources change.
+# WRITE_SIZE x1.00: the factors a plain 512 MiB device copy gives), mean over the stage
+# launches of SSP-RK3 substeps (all three stages; not the single applications a profiled run
+# makes afterwards, which read no base state); keyed by (config, precision, kernel) with the
+# SHA-256 of the kernel sources the counters were taken on.  Reported as null once those
+# sources change.
 TRAFFIC_SOURCES = ("paper_1508_04245_amd/csrc/conv_kernels.hpp",
                    "paper_1508_04245_amd/csrc/mfma_kernels.hpp",
                    "paper_1508_04245_amd/csrc/dgconv.hip",
